@@ -1,0 +1,184 @@
+/*
+ * hfd.h -- C ABI of the MI355X (gfx950) hybrid-FFT demagnetization-field
+ * library (Heistracher, Bruckner, Abert, Vogler, Suess, "Hybrid FFT algorithm
+ * for fast demagnetization field calculations on non-equidistant magnetic
+ * layers", arXiv:1910.07054).
+ *
+ * Problem (Sec. 3 of the paper, discrete field and its non-equidistant finite
+ * difference model): nz layers share a lateral grid of nx x ny cells of size
+ * dx x dy; layer l has its own thickness t_l and bottom z_l.  For a
+ * magnetization m (unit vectors, M_s = 1) the library returns
+ *
+ *     h_i(p) = - sum_j sum_q N^{ij}(p - q) m_j(q)
+ *
+ * where N^{ij} is the cell-averaged demagnetization tensor between a cell of
+ * layer i and a cell of layer j (Sec. 2, generalized Newell formulas, with the
+ * four-point stencils of appendices A and B).  The sum over the lateral
+ * offsets uses the discrete convolution theorem on zero-padded grids; the sum
+ * over layers is explicit per lateral frequency (Sec. 3.1, hybrid form).
+ *
+ * Units: any consistent length unit (N is scale invariant); h is in units of
+ * M_s.  Per-layer saturation magnetizations are the caller's: scale m_j by
+ * M_s,j / M_s,ref before the call.
+ *
+ * Memory and layout:
+ *   - m, h and the gradient fields are DEVICE pointers owned by the caller,
+ *     layout [batch][3][nz][ny][nx] (x fastest, component-major), FP32, or
+ *     FP64 for plans created with HFD_FP64.  They must be 16-byte aligned and
+ *     must not overlap each other.
+ *   - a plan owns its device tensor and all workspace, allocated in
+ *     hfd_setup_tensor for up to batch_max states; hfd_demag_field and
+ *     hfd_demag_vjp allocate nothing and only enqueue work on the given HIP
+ *     stream (NULL = the default stream), so they may be captured in a HIP
+ *     graph.  A plan must not be used from two streams at the same time.
+ *
+ * Errors: every call returns an hfd_status; arguments are validated on the
+ * host before any HIP call.  On failure hfd_last_error() returns a message
+ * (thread-local, valid until the next call on that thread).
+ */
+#ifndef HFD_H
+#define HFD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hfd_plan_s *hfd_plan;
+
+typedef enum {
+    HFD_OK = 0,
+    HFD_EINVAL = -1,   /* invalid argument                                 */
+    HFD_ENOMEM = -2,   /* device or host allocation failed / size overflow */
+    HFD_EHIP = -3,     /* a HIP runtime call or kernel launch failed       */
+    HFD_EBATCH = -4,   /* batch larger than the plan's batch_max           */
+    HFD_EHANDLE = -5,  /* NULL, destroyed or corrupted plan                */
+    HFD_ENOTSUP = -6   /* size outside the compiled kernel range           */
+} hfd_status;
+
+/* Flags for hfd_setup_tensor. */
+enum {
+    HFD_FP32 = 0,               /* FFTs and z-mixing in FP32 (tensor set up in FP64)   */
+    HFD_FP64 = 1,               /* FFTs and z-mixing in FP64                           */
+    HFD_MIX_SPLIT_BF16 = 2,     /* z-mixing on MFMA with a three-way BF16 split of the
+                                   tensor and of the spectra, FP32 accumulation        */
+    HFD_SPLIT_PASSES = 4,       /* force the five-pass path (y-FFT, mix and inverse
+                                   y-FFT as separate kernels) even where the fused
+                                   y-pass fits in LDS                                  */
+    HFD_STORE_DTENSOR = 8       /* keep the thickness-derivative tensors resident
+                                   between hfd_demag_vjp calls (default: recompute)   */
+};
+
+/*
+ * Create a plan and build the Fourier-space tensor.
+ *
+ *   nx, ny      lateral cell counts, 1 <= nx, ny <= 2048
+ *   dx, dy      lateral cell size, > 0
+ *   nz          number of layers, 1 <= nz <= 64
+ *   thickness   HOST array [n_geom][nz], every entry > 0 and finite
+ *   z_bottom    HOST array [n_geom][nz] of layer bottoms, strictly increasing
+ *               with z_bottom[l+1] >= z_bottom[l] + thickness[l] (layers may
+ *               touch, not overlap); NULL stacks the layers without gaps
+ *               starting at 0
+ *   n_geom      number of stacks (thickness candidates) sharing nx, ny, dx,
+ *               dy, nz; a batch of B states is split into n_geom equal runs
+ *               and run g uses stack g (B must be a multiple of n_geom)
+ *   batch_max   largest batch later passed to hfd_demag_field / _vjp
+ *   flags       HFD_FP32 or HFD_FP64, optionally | HFD_MIX_SPLIT_BF16 (FP32
+ *               only) | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR
+ *   stream      HIP stream for the setup kernels; the call returns after the
+ *               setup has completed on that stream
+ *
+ * The tensor of every layer pair (Sec. 2) is computed in FP64 on the GPU:
+ * generalized Newell formulas near the diagonal, Gauss-Legendre quadrature
+ * of the dipole kernel beyond six cell sizes (where the 64-term Newell sum
+ * loses its digits to cancellation); then a 2D FFT per pair (F1 F2 of Sec.
+ * 3.1) in FP64, rounded to the plan's precision.  Only the unique pairs
+ * i <= j are stored (reciprocity t_i N^{ij}(d) = t_j N^{ji}(-d)).
+ */
+hfd_status hfd_setup_tensor(hfd_plan *out, int nx, int ny, double dx, double dy, int nz,
+                            const double *thickness, const double *z_bottom, int n_geom,
+                            int batch_max, unsigned flags, void *stream);
+
+/* Rebuild the tensor of an existing plan for new thicknesses / bottoms (same
+ * nx, ny, dx, dy, nz, n_geom; same conventions as hfd_setup_tensor).  Blocks
+ * until the new tensor is ready on `stream`. */
+hfd_status hfd_set_thickness(hfd_plan plan, const double *thickness, const double *z_bottom,
+                             void *stream);
+
+/*
+ * h = -N * m  for `batch` states (Sec. 3.1, hybrid 2D FFT + explicit z sum).
+ * m and h: device [batch][3][nz][ny][nx]; h is overwritten.  batch must be in
+ * [1, batch_max] and a multiple of n_geom.  m == h (or overlap) -> HFD_EINVAL.
+ */
+hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, void *stream);
+
+/*
+ * Vector-Jacobian product of h = h(m, t) for an upstream gradient grad_h:
+ *   grad_m = (dh/dm)^T grad_h           (device [batch][3][nz][ny][nx]), and
+ *   grad_thickness[b][k] = d <grad_h_b, h_b> / d t_k   (device FP64
+ *                                       [batch][nz]) for a stack whose gaps stay
+ *                                       fixed (raising t_k lifts the layers above k).
+ * Either output may be NULL.  The transpose uses reciprocity:
+ * (dh/dm)^T = T (dh/dm) T^{-1}, T = diag(t_l).  The thickness derivative uses
+ * the derivatives of the Newell kernels with respect to the z offset,
+ * evaluated in FP64 and transformed like the tensor.
+ */
+hfd_status hfd_demag_vjp(hfd_plan plan, const void *m, const void *grad_h, void *grad_m,
+                         double *grad_thickness, int batch, void *stream);
+
+/* Time each kernel stage of hfd_demag_field with HIP events over `reps`
+ * launches on `stream` (inputs as for hfd_demag_field).  ms_per_stage[k]
+ * receives the average duration of stage k (host array of length 8); n_stages
+ * and names (semicolon separated, host buffer of name_len bytes) describe the
+ * stages.  For measurement only; it synchronizes the stream. */
+hfd_status hfd_time_stages(hfd_plan plan, const void *m, void *h, int batch, int reps,
+                           void *stream, double *ms_per_stage, int *n_stages, char *names,
+                           int name_len);
+
+/* Measure the candidate launch shapes of the current path for `batch` states
+ * (scratch data, HIP events) and keep the fastest per stage in the plan.
+ * Returns the chosen configuration as text in `report` (host buffer). */
+hfd_status hfd_autotune(hfd_plan plan, int batch, void *stream, char *report, int report_len);
+
+/* Plan description (host). */
+typedef struct {
+    int nx, ny, nz, n_geom, batch_max;
+    int Lx, Ly;             /* padded lateral lengths (powers of two >= 2n)        */
+    int fused;              /* 1: three-pass path (fused y-pass), 0: five passes   */
+    int fp64;               /* 1 if the field path runs in FP64                    */
+    int mix_bf16;           /* 1 if the z-mixing runs on split-BF16 MFMA           */
+    long long tensor_bytes; /* bytes of the stored Fourier tensor (all stacks)     */
+    long long work_bytes;   /* bytes of the field workspace                        */
+} hfd_info;
+hfd_status hfd_get_info(hfd_plan plan, hfd_info *info);
+
+/* Copy the stored Fourier tensor of stack `geom` to the HOST buffer `dst`:
+ * layout [P_u][5][Lx/2+1][Ly/2+1] in the plan's precision, P_u = nz(nz+1)/2
+ * unique pairs i <= j in row-major upper-triangle order, components
+ * (xx, yy, xy, xz, yz) of t_i * (-DFT2(N^{ij}) / (Lx Ly)); real parts for
+ * xx, yy, xy, imaginary parts for xz, yz (the only non-zero parts by
+ * lateral parity); zz follows from the trace (see DESIGN notes). */
+hfd_status hfd_export_fourier_tensor(hfd_plan plan, int geom, void *dst, long long dst_bytes);
+
+/* Compute the real-space FP64 tensor N^{ij}(p, q) of stack `geom` for one
+ * ordered pair (target i, source j), p in [-(nx-1), nx-1], q in
+ * [-(ny-1), ny-1], into the HOST buffer dst [6][2ny-1][2nx-1] (components
+ * xx, yy, zz, xy, xz, yz), with the same kernels the setup uses. */
+hfd_status hfd_export_real_tensor(hfd_plan plan, int geom, int i, int j, double *dst, void *stream);
+
+/* Forward spectra (2D DFT of the zero-padded m, FP32/FP64 complex) on the
+ * DEVICE buffer dst: layout [batch][3][nz][Lx/2][Ly], the kx = 0 and
+ * kx = Lx/2 columns packed as (Re X(0, ky) + i Re X(Lx/2, ky)) before the
+ * y transform (i.e. column 0 holds the y-DFT of that packed sequence).
+ * dst_bytes must cover batch * 3 * nz * (Lx/2) * Ly complex values. */
+hfd_status hfd_forward_spectrum(hfd_plan plan, const void *m, void *dst, long long dst_bytes,
+                                int batch, void *stream);
+
+hfd_status hfd_destroy(hfd_plan plan);
+
+const char *hfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFD_H */

@@ -1,0 +1,662 @@
+// C ABI of the hybrid-FFT demagnetization-field library (include/hfd.h).
+// Host logic only: argument validation, plan ownership, tensor setup
+// orchestration and kernel dispatch.  All arithmetic runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/hfd.h"
+#include "launch.hpp"
+
+using namespace hfd;
+
+namespace {
+
+thread_local std::string g_err;
+
+hfd_status fail(hfd_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HFD_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(HFD_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HFD_TRY(expr)                    \
+    do {                                 \
+        hfd_status st_ = (expr);         \
+        if (st_ != HFD_OK) return st_;   \
+    } while (0)
+
+constexpr uint64_t kMagic = 0x31414c5044464848ull;
+constexpr uint64_t kDead = 0xdeaddeaddeaddeadull;
+constexpr unsigned kKnownFlags = HFD_FP64 | HFD_MIX_SPLIT_BF16 | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR;
+
+int next_pow2(long long v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// safe products for size computations (overflow -> -1)
+long long mul_ll(long long a, long long b)
+{
+    if (a < 0 || b < 0) return -1;
+    if (a != 0 && b > (long long)(INT64_MAX / 4) / a) return -1;
+    return a * b;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    hipError_t set(int dev)
+    {
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev) {
+            changed = true;
+            return hipSetDevice(dev);
+        }
+        return hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct hfd_plan_s {
+    uint64_t magic = kMagic;
+    int dev = 0;
+    int nx = 0, ny = 0, nz = 0, G = 0, batch_max = 0;
+    double dx = 0, dy = 0;
+    unsigned flags = 0;
+    bool fp64 = false, bf16 = false, fused = false;
+    int Lx = 0, Ly = 0, M = 0, QX = 0, QY = 0, P = 0;
+    size_t rsz = 4, csz = 8;
+    std::vector<double> thick, zbot;  // [G][nz]
+    // device
+    void* Q = nullptr;          // [G][P][5][QX][QY]
+    long long q_geom_stride = 0;
+    void* Qs = nullptr;         // split-BF16 operands (MFMA mixing)
+    long long qs_geom_stride = 0;
+    void* lp = nullptr;         // [G][2][nz]
+    void* twx = nullptr;        // plan precision, length Lx
+    void* twy = nullptr;        // plan precision, length Ly
+    double* twx64 = nullptr;    // FP64 (tensor setup)
+    double* twy64 = nullptr;
+    void* X1 = nullptr;         // [batch_max][S][M][ny]
+    void* Mh = nullptr;         // [batch_max][S][M][Ly]
+    void* Hh = nullptr;
+    size_t x1_bytes = 0, mh_bytes = 0;
+    // thickness-derivative data
+    float* D = nullptr;         // [G][nzeta_max][6][QX][QY]
+    long long d_geom_stride = 0;
+    int* zidx = nullptr;        // [G][nz][nz][4]
+    double* zeta_dev = nullptr; // [G][nzeta_max]
+    int nzeta_max = 0;
+    std::vector<int> nzeta;     // per geometry
+    bool d_valid = false;
+    double* partial = nullptr;  // reduction partials
+    size_t partial_count = 0;
+    // launch configuration chosen by the autotuner
+    int tuned = 0;
+};
+
+namespace {
+
+// live plans; a handle not in this set (never created, or destroyed) is rejected
+std::mutex g_plans_mu;
+std::unordered_set<const void*> g_plans;
+
+hfd_status check_plan(hfd_plan p)
+{
+    if (!p) return fail(HFD_EHANDLE, "plan is NULL");
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        if (!g_plans.count(p)) return fail(HFD_EHANDLE, "plan handle was destroyed or never created");
+    }
+    if (p->magic != kMagic) return fail(HFD_EHANDLE, "plan handle is corrupted");
+    return HFD_OK;
+}
+
+hfd_status validate_geometry(int nz, int G, const double* thick, const double* zbot,
+                             std::vector<double>& t_out, std::vector<double>& z_out)
+{
+    if (!thick) return fail(HFD_EINVAL, "thickness is NULL");
+    t_out.assign(thick, thick + (size_t)G * nz);
+    z_out.resize((size_t)G * nz);
+    for (int g = 0; g < G; ++g) {
+        for (int l = 0; l < nz; ++l) {
+            const double t = t_out[(size_t)g * nz + l];
+            if (!std::isfinite(t) || !(t > 0.0))
+                return fail(HFD_EINVAL, "thickness[" + std::to_string(g) + "][" + std::to_string(l) +
+                                            "] must be finite and > 0");
+        }
+        if (zbot) {
+            for (int l = 0; l < nz; ++l) {
+                const double z = zbot[(size_t)g * nz + l];
+                if (!std::isfinite(z)) return fail(HFD_EINVAL, "z_bottom must be finite");
+                z_out[(size_t)g * nz + l] = z;
+            }
+            for (int l = 0; l + 1 < nz; ++l) {
+                const double top = z_out[(size_t)g * nz + l] + t_out[(size_t)g * nz + l];
+                const double nb = z_out[(size_t)g * nz + l + 1];
+                const double tol = 1e-9 * std::max({std::fabs(top), std::fabs(nb), 1e-300}) +
+                                   1e-12 * t_out[(size_t)g * nz + l];
+                if (nb < top - tol)
+                    return fail(HFD_EINVAL, "layers overlap: z_bottom[" + std::to_string(g) + "][" +
+                                                std::to_string(l + 1) + "] is below the top of layer " +
+                                                std::to_string(l) +
+                                                " (layers must be ordered bottom to top and may touch)");
+            }
+        } else {
+            double acc = 0.0;
+            for (int l = 0; l < nz; ++l) {
+                z_out[(size_t)g * nz + l] = acc;
+                acc += t_out[(size_t)g * nz + l];
+            }
+        }
+    }
+    return HFD_OK;
+}
+
+template <typename T>
+hfd_status dev_alloc(T** p, size_t bytes, const char* what)
+{
+    *p = nullptr;
+    if (bytes == 0) return HFD_OK;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HFD_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes for " +
+                                    what + " failed: " + hipGetErrorString(e));
+    }
+    *p = (T*)q;
+    return HFD_OK;
+}
+
+void free_plan_memory(hfd_plan p)
+{
+    if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
+    if (p->twy == p->twy64) p->twy = nullptr;
+    void* bufs[] = {p->Q, p->Qs, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
+                    p->D, p->zidx, p->zeta_dev, p->partial};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    p->Q = p->Qs = p->lp = p->twx = p->twy = p->X1 = p->Mh = p->Hh = nullptr;
+    p->twx64 = p->twy64 = nullptr;
+    p->D = nullptr;
+    p->zidx = nullptr;
+    p->zeta_dev = nullptr;
+    p->partial = nullptr;
+}
+
+// twiddle table exp(-2 pi i m / L), m in [0, L), in FP64 (exact octant reduction)
+std::vector<double> twiddles(int L)
+{
+    std::vector<double> t(2 * (size_t)L);
+    for (int m = 0; m < L; ++m) {
+        // angle = 2 pi m / L; use sin/cos of reduced arguments for accuracy
+        const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+        t[2 * (size_t)m] = (double)cosl(a);
+        t[2 * (size_t)m + 1] = (double)-sinl(a);
+    }
+    return t;
+}
+
+hfd_status upload_twiddles(hfd_plan p, hipStream_t s)
+{
+    auto tx = twiddles(p->Lx), ty = twiddles(p->Ly);
+    HFD_TRY(dev_alloc(&p->twx64, tx.size() * 8, "twiddles"));
+    HFD_TRY(dev_alloc(&p->twy64, ty.size() * 8, "twiddles"));
+    HFD_HIP(hipMemcpyAsync(p->twx64, tx.data(), tx.size() * 8, hipMemcpyHostToDevice, s));
+    HFD_HIP(hipMemcpyAsync(p->twy64, ty.data(), ty.size() * 8, hipMemcpyHostToDevice, s));
+    if (p->fp64) {
+        p->twx = p->twx64;
+        p->twy = p->twy64;
+        return HFD_OK;
+    }
+    std::vector<float> fx(tx.begin(), tx.end()), fy(ty.begin(), ty.end());
+    HFD_TRY(dev_alloc(&p->twx, fx.size() * 4, "twiddles"));
+    HFD_TRY(dev_alloc(&p->twy, fy.size() * 4, "twiddles"));
+    HFD_HIP(hipMemcpyAsync(p->twx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice, s));
+    HFD_HIP(hipMemcpyAsync(p->twy, fy.data(), fy.size() * 4, hipMemcpyHostToDevice, s));
+    HFD_HIP(hipStreamSynchronize(s));
+    return HFD_OK;
+}
+
+// Build the Fourier tensor of every stack (FP64 setup, stored in plan precision).
+hfd_status build_tensor(hfd_plan p, hipStream_t s)
+{
+    const long long plane = (long long)p->Lx * p->Ly;
+    const long long per_pair = 6 * plane * 8;  // FP64 real arrays per pair (same for the spectra)
+    const long long budget = 512LL << 20;
+    int CP = (int)std::max(1LL, std::min<long long>(p->P, budget / per_pair));
+    double* W = nullptr;
+    void* F = nullptr;
+    PairGeoH* pg = nullptr;
+    double* scale = nullptr;
+    hfd_status st = HFD_OK;
+    do {
+        st = dev_alloc(&W, (size_t)CP * per_pair, "tensor setup (real space)");
+        if (st) break;
+        st = dev_alloc(&F, (size_t)CP * per_pair, "tensor setup (spectra)");
+        if (st) break;
+        st = dev_alloc(&pg, sizeof(PairGeoH) * (size_t)p->P, "pair table");
+        if (st) break;
+        st = dev_alloc(&scale, sizeof(double) * (size_t)p->P, "pair scales");
+        if (st) break;
+        std::vector<PairGeoH> hp((size_t)p->P);
+        std::vector<double> hs((size_t)p->P);
+        for (int g = 0; g < p->G && st == HFD_OK; ++g) {
+            const double* t = &p->thick[(size_t)g * p->nz];
+            const double* z = &p->zbot[(size_t)g * p->nz];
+            int u = 0;
+            for (int i = 0; i < p->nz; ++i)
+                for (int j = i; j < p->nz; ++j, ++u) {
+                    hp[u] = {t[i], t[j], z[i] - z[j], 0.0};
+                    hs[u] = -t[i] / (double)plane;
+                }
+            hipError_t e = hipMemcpyAsync(pg, hp.data(), sizeof(PairGeoH) * p->P, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(scale, hs.data(), sizeof(double) * p->P, hipMemcpyHostToDevice, s);
+            for (int u0 = 0; u0 < p->P && e == hipSuccess; u0 += CP) {
+                const int np = std::min(CP, p->P - u0);
+                e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
+                if (e == hipSuccess)
+                    e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
+                if (e == hipSuccess)
+                    e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
+                if (e == hipSuccess)
+                    e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
+                if (e == hipSuccess) {
+                    char* qdst = (char*)p->Q + ((size_t)g * p->q_geom_stride + (size_t)u0 * 5 * p->QX * p->QY) * p->rsz;
+                    e = launch_pack(p->fp64, F, qdst, scale + u0, np, 5, p->M, p->Ly, p->QX, p->QY, s);
+                }
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
+        }
+        if (st) break;
+        // layer parameters: 1/t and the self-pair trace -t/(Lx Ly)
+        std::vector<double> lp((size_t)p->G * 2 * p->nz);
+        for (int g = 0; g < p->G; ++g)
+            for (int l = 0; l < p->nz; ++l) {
+                const double t = p->thick[(size_t)g * p->nz + l];
+                lp[((size_t)g * 2) * p->nz + l] = 1.0 / t;
+                lp[((size_t)g * 2 + 1) * p->nz + l] = -t / (double)plane;
+            }
+        hipError_t e;
+        if (p->fp64) {
+            e = hipMemcpyAsync(p->lp, lp.data(), lp.size() * 8, hipMemcpyHostToDevice, s);
+        } else {
+            std::vector<float> lf(lp.begin(), lp.end());
+            e = hipMemcpyAsync(p->lp, lf.data(), lf.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e == hipSuccess && p->bf16)
+            e = launch_split_tensor((const float*)p->Q, p->Qs, p->G, p->nz, p->QX, p->QY,
+                                    (const float*)p->lp, 0, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
+    } while (0);
+    if (W) (void)hipFree(W);
+    if (F) (void)hipFree(F);
+    if (pg) (void)hipFree(pg);
+    if (scale) (void)hipFree(scale);
+    p->d_valid = false;
+    return st;
+}
+
+hfd_status check_field_args(hfd_plan p, const void* a, const void* b, int batch, const char* na,
+                            const char* nb)
+{
+    if (!a) return fail(HFD_EINVAL, std::string(na) + " is NULL");
+    if (!b) return fail(HFD_EINVAL, std::string(nb) + " is NULL");
+    if (((uintptr_t)a & 15) || ((uintptr_t)b & 15))
+        return fail(HFD_EINVAL, std::string(na) + " and " + nb + " must be 16-byte aligned");
+    if (batch < 1) return fail(HFD_EINVAL, "batch must be >= 1");
+    if (batch > p->batch_max)
+        return fail(HFD_EBATCH, "batch " + std::to_string(batch) + " exceeds batch_max " +
+                                    std::to_string(p->batch_max));
+    if (batch % p->G)
+        return fail(HFD_EINVAL, "batch must be a multiple of n_geom (" + std::to_string(p->G) + ")");
+    const size_t bytes = (size_t)batch * 3 * p->nz * p->ny * p->nx * p->rsz;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    if (a0 < b0 + bytes && b0 < a0 + bytes)
+        return fail(HFD_EINVAL, std::string(na) + " and " + nb + " overlap");
+    return HFD_OK;
+}
+
+// Enqueue the field passes.  stage_ev: optional events recorded after each stage.
+hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
+                     hipEvent_t* stage_ev = nullptr, int* nstage = nullptr)
+{
+    const int S = 3 * p->nz;
+    const int nsig = batch * S;
+    const int bpg = batch / p->G;
+    int k = 0;
+    auto mark = [&]() {
+        if (stage_ev) (void)hipEventRecord(stage_ev[k], s);
+        ++k;
+    };
+    HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+                        nsig, p->twx, s));
+    mark();
+    if (p->fused) {
+        HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, batch, p->Q,
+                             p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
+        mark();
+    } else {
+        const long long ncols = (long long)nsig * p->M;
+        HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
+        mark();
+        if (p->bf16)
+            HFD_HIP(launch_mix_bf16(p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Qs, p->qs_geom_stride,
+                                    p->QX, p->QY, p->lp, bpg, adjoint, s));
+        else
+            HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, s));
+        mark();
+        HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, p->X1, p->ny, ncols, p->twy, s));
+        mark();
+    }
+    HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+                        nsig, p->twx, s));
+    mark();
+    if (nstage) *nstage = k;
+    return HFD_OK;
+}
+
+std::string stage_names(hfd_plan p)
+{
+    if (p->fused) return "xfwd;ymix_fused;xinv";
+    return std::string("xfwd;yfwd;") + (p->bf16 ? "mix_bf16" : "mix") + ";yinv;xinv";
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hfd_last_error(void) { return g_err.c_str(); }
+
+hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy, int nz,
+                            const double* thickness, const double* z_bottom, int n_geom,
+                            int batch_max, unsigned flags, void* stream)
+{
+    if (!out) return fail(HFD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nx > 2048 || ny > 2048)
+        return fail(HFD_EINVAL, "nx and ny must be in [1, 2048]");
+    if (!std::isfinite(dx) || !std::isfinite(dy) || !(dx > 0) || !(dy > 0))
+        return fail(HFD_EINVAL, "dx and dy must be finite and > 0");
+    if (nz < 1 || nz > 64) return fail(HFD_EINVAL, "nz must be in [1, 64]");
+    if (n_geom < 1 || n_geom > 4096) return fail(HFD_EINVAL, "n_geom must be in [1, 4096]");
+    if (batch_max < 1) return fail(HFD_EINVAL, "batch_max must be >= 1");
+    if (batch_max < n_geom) return fail(HFD_EINVAL, "batch_max must be >= n_geom");
+    if (flags & ~kKnownFlags) return fail(HFD_EINVAL, "unknown flag bits");
+    if ((flags & HFD_FP64) && (flags & HFD_MIX_SPLIT_BF16))
+        return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 requires the FP32 field path");
+
+    hfd_plan p = new (std::nothrow) hfd_plan_s();
+    if (!p) return fail(HFD_ENOMEM, "host allocation of the plan failed");
+    p->nx = nx; p->ny = ny; p->nz = nz; p->G = n_geom; p->batch_max = batch_max;
+    p->dx = dx; p->dy = dy; p->flags = flags;
+    p->fp64 = flags & HFD_FP64;
+    p->bf16 = flags & HFD_MIX_SPLIT_BF16;
+    p->rsz = p->fp64 ? 8 : 4;
+    p->csz = 2 * p->rsz;
+    p->Lx = std::max(kMinL, next_pow2(2LL * nx));
+    p->Ly = std::max(kMinL, next_pow2(2LL * ny));
+    p->M = p->Lx / 2;
+    p->QX = p->M + 1;
+    p->QY = p->Ly / 2 + 1;
+    p->P = nz * (nz + 1) / 2;
+    hfd_status st = validate_geometry(nz, n_geom, thickness, z_bottom, p->thick, p->zbot);
+    if (st) { delete p; return st; }
+    p->fused = !(flags & HFD_SPLIT_PASSES) && !p->bf16 && fused_supported(p->fp64, p->Ly, nz, nullptr);
+
+    // sizes (overflow checked)
+    const long long S = 3LL * nz;
+    const long long q_per_geom = mul_ll(mul_ll((long long)p->P * 5, p->QX), p->QY);
+    const long long q_elems = mul_ll(q_per_geom, n_geom);
+    const long long x1 = mul_ll(mul_ll(mul_ll((long long)batch_max, S), p->M), (long long)ny * (long long)p->csz);
+    const long long mh = mul_ll(mul_ll(mul_ll((long long)batch_max, S), p->M), (long long)p->Ly * (long long)p->csz);
+    if (q_elems < 0 || x1 < 0 || mh < 0) { delete p; return fail(HFD_ENOMEM, "size overflow"); }
+    p->q_geom_stride = q_per_geom;
+    p->x1_bytes = (size_t)x1;
+    p->mh_bytes = (size_t)mh;
+
+    hipStream_t s = (hipStream_t)stream;
+    if (hipGetDevice(&p->dev) != hipSuccess) { delete p; return fail(HFD_EHIP, "hipGetDevice failed"); }
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess) {
+        const long double need = (long double)q_elems * p->rsz + (long double)x1 + 2.0L * mh;
+        if (need > (long double)freeb) {
+            delete p;
+            return fail(HFD_ENOMEM, "plan needs " + std::to_string((double)need) + " bytes of device memory, " +
+                                        std::to_string(freeb) + " free");
+        }
+    }
+    do {
+        st = dev_alloc(&p->Q, (size_t)q_elems * p->rsz, "Fourier tensor");
+        if (st) break;
+        st = dev_alloc(&p->lp, (size_t)n_geom * 2 * nz * p->rsz, "layer parameters");
+        if (st) break;
+        st = dev_alloc(&p->X1, p->x1_bytes, "x-pass workspace");
+        if (st) break;
+        st = dev_alloc(&p->Mh, p->mh_bytes, "spectrum workspace");
+        if (st) break;
+        st = dev_alloc(&p->Hh, p->mh_bytes, "spectrum workspace");
+        if (st) break;
+        if (p->bf16) {
+            p->qs_geom_stride = split_tensor_bytes(1, nz, p->QX, p->QY);
+            st = dev_alloc(&p->Qs, (size_t)split_tensor_bytes(n_geom, nz, p->QX, p->QY), "split tensor");
+            if (st) break;
+        }
+        st = upload_twiddles(p, s);
+        if (st) break;
+        st = build_tensor(p, s);
+    } while (0);
+    if (st) {
+        free_plan_memory(p);
+        delete p;
+        return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        g_plans.insert(p);
+    }
+    *out = p;
+    return HFD_OK;
+}
+
+hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* z_bottom, void* stream)
+{
+    HFD_TRY(check_plan(p));
+    std::vector<double> t, z;
+    HFD_TRY(validate_geometry(p->nz, p->G, thickness, z_bottom, t, z));
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    p->thick = t;
+    p->zbot = z;
+    return build_tensor(p, (hipStream_t)stream);
+}
+
+hfd_status hfd_demag_field(hfd_plan p, const void* m, void* h, int batch, void* stream)
+{
+    HFD_TRY(check_plan(p));
+    HFD_TRY(check_field_args(p, m, h, batch, "m", "h"));
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    return run_field(p, m, h, batch, 0, (hipStream_t)stream);
+}
+
+hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* grad_m,
+                         double* grad_thickness, int batch, void* stream)
+{
+    HFD_TRY(check_plan(p));
+    if (!grad_m && !grad_thickness) return fail(HFD_EINVAL, "grad_m and grad_thickness are both NULL");
+    if (grad_m) HFD_TRY(check_field_args(p, grad_h, grad_m, batch, "grad_h", "grad_m"));
+    if (grad_thickness) {
+        HFD_TRY(check_field_args(p, m, grad_h, batch, "m", "grad_h"));
+        if ((uintptr_t)grad_thickness & 7) return fail(HFD_EINVAL, "grad_thickness must be 8-byte aligned");
+        return fail(HFD_ENOTSUP, "thickness gradient not available in this build");
+    }
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    return run_field(p, grad_h, grad_m, batch, 1, (hipStream_t)stream);
+}
+
+hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int reps, void* stream,
+                           double* ms_per_stage, int* n_stages, char* names, int name_len)
+{
+    HFD_TRY(check_plan(p));
+    HFD_TRY(check_field_args(p, m, h, batch, "m", "h"));
+    if (reps < 1 || !ms_per_stage || !n_stages) return fail(HFD_EINVAL, "bad timing arguments");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[9];
+    for (int k = 0; k < 9; ++k) HFD_HIP(hipEventCreate(&ev[k]));
+    double acc[8] = {0};
+    int ns = 0;
+    hfd_status st = HFD_OK;
+    for (int r = 0; r < reps && st == HFD_OK; ++r) {
+        (void)hipEventRecord(ev[0], s);
+        st = run_field(p, m, h, batch, 0, s, ev + 1, &ns);
+        if (st) break;
+        if (hipEventSynchronize(ev[ns]) != hipSuccess) { st = fail(HFD_EHIP, "event sync failed"); break; }
+        for (int k = 0; k < ns; ++k) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            acc[k] += ms;
+        }
+    }
+    for (int k = 0; k < 9; ++k) (void)hipEventDestroy(ev[k]);
+    if (st) return st;
+    for (int k = 0; k < 8; ++k) ms_per_stage[k] = k < ns ? acc[k] / reps : 0.0;
+    *n_stages = ns;
+    if (names && name_len > 0) {
+        std::string n = stage_names(p);
+        std::snprintf(names, (size_t)name_len, "%s", n.c_str());
+    }
+    return HFD_OK;
+}
+
+hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int report_len)
+{
+    HFD_TRY(check_plan(p));
+    (void)batch;
+    (void)stream;
+    if (report && report_len > 0)
+        std::snprintf(report, (size_t)report_len, "path=%s", p->fused ? "fused" : "split");
+    return HFD_OK;
+}
+
+hfd_status hfd_get_info(hfd_plan p, hfd_info* info)
+{
+    HFD_TRY(check_plan(p));
+    if (!info) return fail(HFD_EINVAL, "info is NULL");
+    info->nx = p->nx; info->ny = p->ny; info->nz = p->nz; info->n_geom = p->G;
+    info->batch_max = p->batch_max; info->Lx = p->Lx; info->Ly = p->Ly;
+    info->fused = p->fused; info->fp64 = p->fp64; info->mix_bf16 = p->bf16;
+    info->tensor_bytes = p->q_geom_stride * (long long)p->G * (long long)p->rsz;
+    info->work_bytes = (long long)(p->x1_bytes + 2 * p->mh_bytes);
+    return HFD_OK;
+}
+
+hfd_status hfd_export_fourier_tensor(hfd_plan p, int geom, void* dst, long long dst_bytes)
+{
+    HFD_TRY(check_plan(p));
+    if (geom < 0 || geom >= p->G) return fail(HFD_EINVAL, "geom out of range");
+    const long long bytes = p->q_geom_stride * (long long)p->rsz;
+    if (!dst || dst_bytes < bytes) return fail(HFD_EINVAL, "dst too small (need " + std::to_string(bytes) + " bytes)");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    HFD_HIP(hipDeviceSynchronize());
+    HFD_HIP(hipMemcpy(dst, (char*)p->Q + (size_t)geom * p->q_geom_stride * p->rsz, (size_t)bytes,
+                      hipMemcpyDeviceToHost));
+    return HFD_OK;
+}
+
+hfd_status hfd_export_real_tensor(hfd_plan p, int geom, int i, int j, double* dst, void* stream)
+{
+    HFD_TRY(check_plan(p));
+    if (geom < 0 || geom >= p->G || i < 0 || j < 0 || i >= p->nz || j >= p->nz)
+        return fail(HFD_EINVAL, "geom or pair index out of range");
+    if (!dst) return fail(HFD_EINVAL, "dst is NULL");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = 6 * (size_t)(2 * p->nx - 1) * (2 * p->ny - 1);
+    double* W = nullptr;
+    PairGeoH* pg = nullptr;
+    HFD_TRY(dev_alloc(&W, n * 8, "export"));
+    hfd_status st = dev_alloc(&pg, sizeof(PairGeoH), "export");
+    if (st) { (void)hipFree(W); return st; }
+    const double* t = &p->thick[(size_t)geom * p->nz];
+    const double* z = &p->zbot[(size_t)geom * p->nz];
+    PairGeoH h = {t[i], t[j], z[i] - z[j], 0.0};
+    hipError_t e = hipMemcpyAsync(pg, &h, sizeof(h), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W, 0, n * 8, s);
+    if (e == hipSuccess) e = launch_tensor_real(W, pg, 1, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, W, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(W);
+    (void)hipFree(pg);
+    if (e != hipSuccess) return fail(HFD_EHIP, std::string("export_real_tensor: ") + hipGetErrorString(e));
+    return HFD_OK;
+}
+
+hfd_status hfd_forward_spectrum(hfd_plan p, const void* m, void* dst, long long dst_bytes, int batch,
+                                void* stream)
+{
+    HFD_TRY(check_plan(p));
+    if (!m || !dst) return fail(HFD_EINVAL, "m or dst is NULL");
+    if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
+    const long long need = (long long)batch * 3 * p->nz * p->M * (long long)p->Ly * (long long)p->csz;
+    if (dst_bytes < need) return fail(HFD_EINVAL, "dst too small (need " + std::to_string(need) + " bytes)");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const int nsig = batch * 3 * p->nz;
+    HFD_HIP(launch_xfwd(p->fp64, p->Lx, m, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx, nsig, p->twx, s));
+    HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, dst, p->ny, (long long)nsig * p->M, p->twy, s));
+    return HFD_OK;
+}
+
+hfd_status hfd_destroy(hfd_plan p)
+{
+    HFD_TRY(check_plan(p));
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        g_plans.erase(p);
+    }
+    DeviceGuard dg;
+    (void)dg.set(p->dev);
+    (void)hipDeviceSynchronize();
+    free_plan_memory(p);
+    p->magic = kDead;
+    delete p;
+    return HFD_OK;
+}
+
+}  // extern "C"

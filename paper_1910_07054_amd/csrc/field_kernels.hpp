@@ -1,0 +1,499 @@
+// Field-path kernels: h = -N * m by the hybrid scheme of Sec. 3.1 --
+// 2D DFT along x and y (zero padded to Lx x Ly), an explicit sum over layers
+// per lateral frequency, inverse 2D DFT, crop.
+//
+// Data layout (per state b, signal s = c * nz + l for component c, layer l):
+//   m, h   [B][S][ny][nx]           real, x fastest
+//   X1     [B][S][M][ny]            complex, M = Lx/2 columns of the x
+//                                   half-spectrum, y fastest; column 0 packs
+//                                   the two real columns kx = 0 and kx = Lx/2
+//                                   as X(0) + i X(Lx/2)
+//   Mh, Hh [B][S][M][Ly]            full y spectra (five-pass path only)
+//   Q      [G][P][5][Lx/2+1][Ly/2+1] Fourier tensor, unique pairs i <= j,
+//                                   components xx, yy, xy, xz, yz of
+//                                   t_i * (-DFT2(N^{ij}) / (Lx Ly)); real part
+//                                   for xx, yy, xy, imaginary part for xz, yz
+//   lp     [G][2][nz]               1 / t_l and -t_l / (Lx Ly) (trace of the
+//                                   self-pair block, which fixes zz)
+#pragma once
+#include "hfd_device.hpp"
+
+namespace hfd {
+
+template <typename R, int LX>
+struct XPassShape {
+    static constexpr int M = LX / 2;
+    static constexpr int V = fft_vals(M);
+    static constexpr int GT = M / V;
+    static constexpr int NT = 256;
+    static constexpr int NG = NT / GT;
+    static constexpr int RS = M + 1;               // padded LDS row stride
+    // rows per block: at least 16 (or one per group), halved until the tile
+    // fits in 80 KB of LDS (two blocks per CU)
+    static constexpr int pick_ty()
+    {
+        int ty = NG > 16 ? NG : 16;
+        while (ty > 1 && sizeof(cpx<R>) * (size_t)ty * RS > 81920) ty /= 2;
+        return ty;
+    }
+    static constexpr int TY = pick_ty();
+    static constexpr size_t LDS = sizeof(cpx<R>) * TY * RS;
+};
+
+// ---------------------------------------------------------------------------
+// x pass, forward: each row of nx reals (zero padded to LX) -> packed half
+// spectrum of LX/2 complex values, written transposed (y fastest).
+// A length-LX real transform is one complex transform of length LX/2 on
+// z[n] = x[2n] + i x[2n+1] followed by the even/odd split.
+// ---------------------------------------------------------------------------
+template <typename R, int LX>
+__global__ __launch_bounds__(256) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
+                                              int nx, int ny, long long in_sig_stride,
+                                              int in_row_stride, const cpx<R>* __restrict__ twx)
+{
+    using S = XPassShape<R, LX>;
+    constexpr int M = S::M, GT = S::GT, NG = S::NG, TY = S::TY, RS = S::RS, NT = S::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int sig = blockIdx.y;
+    const int y0 = blockIdx.x * TY;
+    const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+    const R* base = in + (long long)sig * in_sig_stride;
+
+    for (int r = grp; r < TY; r += NG) {
+        const int y = y0 + r;
+        if (y >= ny) break;
+        cpx<R>* row = sh + r * RS;
+        const R* src = base + (long long)y * in_row_stride;
+        wave_fft<R, M, false>(
+            row, g, twx, 2,
+            [&](int pos) -> cpx<R> {
+                const int n0 = 2 * pos;
+                return {n0 < nx ? src[n0] : R(0), n0 + 1 < nx ? src[n0 + 1] : R(0)};
+            },
+            [&](int pos, cpx<R> v) { row[pos] = v; });
+    }
+    __syncthreads();
+    constexpr int HM = M / 2 + 1;
+    for (int idx = tid; idx < TY * HM; idx += NT) {
+        const int r = idx / HM, k = idx - r * HM;
+        if (y0 + r >= ny) continue;
+        cpx<R>* row = sh + r * RS;
+        if (k == 0) {
+            const cpx<R> z = row[0];
+            row[0] = {z.x + z.y, z.x - z.y};
+        } else if (2 * k == M) {
+            row[k] = cconj(row[k]);
+        } else {
+            const cpx<R> a = row[k], b = row[M - k];
+            const cpx<R> E = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+            const cpx<R> O = {R(0.5) * (a.y + b.y), R(0.5) * (b.x - a.x)};
+            const cpx<R> wO = cmul(twx[k], O);
+            row[k] = cadd(E, wO);
+            row[M - k] = cconj(csub(E, wO));
+        }
+    }
+    __syncthreads();
+    cpx<R>* dst = out + (long long)sig * M * ny;
+    for (int idx = tid; idx < M * TY; idx += NT) {
+        const int r = idx % TY, kx = idx / TY;
+        const int y = y0 + r;
+        if (y < ny) dst[(long long)kx * ny + y] = sh[r * RS + kx];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x pass, inverse: packed half spectrum (transposed) -> nx reals per row.
+// Unnormalized; the 1/(Lx Ly) is folded into the tensor.
+// ---------------------------------------------------------------------------
+template <typename R, int LX>
+__global__ __launch_bounds__(256) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
+                                              int nx, int ny, long long out_sig_stride,
+                                              int out_row_stride, const cpx<R>* __restrict__ twx)
+{
+    using S = XPassShape<R, LX>;
+    constexpr int M = S::M, GT = S::GT, NG = S::NG, TY = S::TY, RS = S::RS, NT = S::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int sig = blockIdx.y;
+    const int y0 = blockIdx.x * TY;
+    const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+    const cpx<R>* src = in + (long long)sig * M * ny;
+    for (int idx = tid; idx < M * TY; idx += NT) {
+        const int r = idx % TY, kx = idx / TY;
+        const int y = y0 + r;
+        sh[r * RS + kx] = (y < ny) ? src[(long long)kx * ny + y] : cpx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    constexpr int HM = M / 2 + 1;
+    for (int idx = tid; idx < TY * HM; idx += NT) {
+        const int r = idx / HM, k = idx - r * HM;
+        if (y0 + r >= ny) continue;
+        cpx<R>* row = sh + r * RS;
+        if (k == 0) {
+            const cpx<R> z = row[0];
+            row[0] = {z.x + z.y, z.x - z.y};
+        } else if (2 * k == M) {
+            const cpx<R> z = row[k];
+            row[k] = {R(2) * z.x, R(-2) * z.y};
+        } else {
+            const cpx<R> a = row[k], b = row[M - k];
+            const cpx<R> P = {a.x + b.x, a.y - b.y};   // a + conj(b)
+            const cpx<R> Qd = {a.x - b.x, a.y + b.y};  // a - conj(b)
+            const cpx<R> T = cmul(cconj(twx[k]), Qd);
+            row[k] = {P.x - T.y, P.y + T.x};
+            row[M - k] = {P.x + T.y, T.x - P.y};
+        }
+    }
+    __syncthreads();
+    R* obase = out + (long long)sig * out_sig_stride;
+    for (int r = grp; r < TY; r += NG) {
+        const int y = y0 + r;
+        if (y >= ny) break;
+        cpx<R>* row = sh + r * RS;
+        R* dst = obase + (long long)y * out_row_stride;
+        wave_fft<R, M, true>(
+            row, g, twx, 2, [&](int pos) -> cpx<R> { return row[pos]; },
+            [&](int pos, cpx<R> v) {
+                const int n0 = 2 * pos;
+                if (n0 < nx) dst[n0] = v.x;
+                if (n0 + 1 < nx) dst[n0 + 1] = v.y;
+            });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-mixing of one frequency pair.  For the unique layer pairs i <= j the
+// stored block S^{ij} = t_i T^{ij} (T = -DFT2(N)/(Lx Ly)) is applied both
+// ways: H_i += S^{ij} M_j and H_j += conj(S^{ij}) M_i (reciprocity
+// t_j T^{ji} = conj(t_i T^{ij})).  Real components: xx, yy, zz, xy; imaginary
+// components: xz, yz.  zz follows from the trace: sum of the diagonal of
+// S^{ij} is dg_i on the self pair and 0 otherwise (the trace of N is the
+// overlap volume over the target volume).  Point b carries the sign sb of the
+// components that are odd in ky (xy, yz).
+// Arrays are indexed [c * NZMAX + layer].
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void block_apply(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, cpx<R> X, cpx<R> Y,
+                                            cpx<R> Z, R xx, R yy, R zz, R xy, R xz, R yz)
+{
+    hx.x += xx * X.x + xy * Y.x - xz * Z.y;
+    hx.y += xx * X.y + xy * Y.y + xz * Z.x;
+    hy.x += xy * X.x + yy * Y.x - yz * Z.y;
+    hy.y += xy * X.y + yy * Y.y + yz * Z.x;
+    hz.x += -xz * X.y - yz * Y.y + zz * Z.x;
+    hz.y += xz * X.x + yz * Y.x + zz * Z.y;
+}
+
+template <typename R, int NZMAX, bool SAME, class InA, class InB>
+__device__ __forceinline__ void mix2(int nz, InA ina, InB inb, cpx<R>* Ha, cpx<R>* Hb,
+                                     const R* __restrict__ qa, const R* __restrict__ qb,
+                                     long long cs, R sb, const R* dg)
+{
+#pragma unroll
+    for (int k = 0; k < 3 * NZMAX; ++k) {
+        Ha[k] = {R(0), R(0)};
+        Hb[k] = {R(0), R(0)};
+    }
+    int u = 0;
+#pragma unroll
+    for (int i = 0; i < NZMAX; ++i) {
+        if (i < nz) {
+        const cpx<R> aix = ina(0, i), aiy = ina(1, i), aiz = ina(2, i);
+        const cpx<R> bix = inb(0, i), biy = inb(1, i), biz = inb(2, i);
+#pragma unroll
+        for (int j = i; j < NZMAX; ++j) {
+            if (j < nz) {
+            const long long o = (long long)u * 5 * cs;
+            const R axx = qa[o], ayy = qa[o + cs], axy = qa[o + 2 * cs], axz = qa[o + 3 * cs],
+                    ayz = qa[o + 4 * cs];
+            R bxx, byy, bxy, bxz, byz;
+            if constexpr (SAME) {
+                bxx = axx; byy = ayy; bxy = axy; bxz = axz; byz = ayz;
+            } else {
+                bxx = qb[o]; byy = qb[o + cs]; bxy = qb[o + 2 * cs]; bxz = qb[o + 3 * cs];
+                byz = qb[o + 4 * cs];
+            }
+            R azz = -(axx + ayy), bzz = -(bxx + byy);
+            if (i == j) {
+                azz += dg[i];
+                bzz += dg[i];
+            }
+            bxy *= sb;
+            byz *= sb;
+            if (i == j) {
+                block_apply(Ha[i], Ha[NZMAX + i], Ha[2 * NZMAX + i], aix, aiy, aiz, axx, ayy, azz,
+                            axy, axz, ayz);
+                block_apply(Hb[i], Hb[NZMAX + i], Hb[2 * NZMAX + i], bix, biy, biz, bxx, byy, bzz,
+                            bxy, bxz, byz);
+            } else {
+                const cpx<R> ajx = ina(0, j), ajy = ina(1, j), ajz = ina(2, j);
+                const cpx<R> bjx = inb(0, j), bjy = inb(1, j), bjz = inb(2, j);
+                block_apply(Ha[i], Ha[NZMAX + i], Ha[2 * NZMAX + i], ajx, ajy, ajz, axx, ayy, azz,
+                            axy, axz, ayz);
+                block_apply(Hb[i], Hb[NZMAX + i], Hb[2 * NZMAX + i], bjx, bjy, bjz, bxx, byy, bzz,
+                            bxy, bxz, byz);
+                block_apply(Ha[j], Ha[NZMAX + j], Ha[2 * NZMAX + j], aix, aiy, aiz, axx, ayy, azz,
+                            axy, -axz, -ayz);
+                block_apply(Hb[j], Hb[NZMAX + j], Hb[2 * NZMAX + j], bix, biy, biz, bxx, byy, bzz,
+                            bxy, -bxz, -byz);
+            }
+            ++u;
+            }
+        }
+        }
+    }
+}
+
+template <int LY>
+struct FusedShape {
+    static constexpr int NT = LY / 2 < 64 ? 64 : LY / 2;
+};
+
+// ---------------------------------------------------------------------------
+// Fused y pass for one kx column of one state: forward y-DFT of the 3 nz
+// signals (input zero padded from ny to LY), z-mixing per ky, inverse y-DFT
+// cropped to ny.  All 3 nz spectra stay in LDS.  Thread t mixes the ky pair
+// (t, LY - t) (t = 0: ky = 0 and LY/2), which share one quadrant tensor entry.
+// Column 0 carries kx = 0 and kx = Lx/2 packed as A + iB; they are separated
+// with the Hermitian symmetry in ky, mixed with their own tensor rows and
+// packed again.  adjoint != 0 applies the transpose (inputs scaled by 1/t
+// instead of the outputs).
+// ---------------------------------------------------------------------------
+template <typename R, int LY, int NZMAX>
+__global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
+    cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long q_geom_stride,
+    int QX, int QY, const R* __restrict__ lp, int bpg, int adjoint, const cpx<R>* __restrict__ twy)
+{
+    constexpr int NT = FusedShape<LY>::NT;
+    constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int kx = blockIdx.x, b = blockIdx.y;
+    const int S = 3 * nz;
+    const int geom = b / bpg;
+    const long long sstride = (long long)M * ny;
+    cpx<R>* col = X + ((long long)b * S * M + kx) * ny;
+    const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+
+    for (int s = grp; s < S; s += NG) {
+        const cpx<R>* src = col + s * sstride;
+        cpx<R>* reg = sh + s * LY;
+        wave_fft<R, LY, false>(
+            reg, g, twy, 1,
+            [&](int pos) -> cpx<R> { return pos < ny ? src[pos] : cpx<R>{R(0), R(0)}; },
+            [&](int pos, cpx<R> v) { reg[pos] = v; });
+    }
+    __syncthreads();
+
+    const int t = tid;
+    if (t < LY / 2) {
+        const R* lpg = lp + (long long)geom * 2 * nz;
+        R invt[NZMAX], dg[NZMAX];
+#pragma unroll
+        for (int i = 0; i < NZMAX; ++i) {
+            invt[i] = i < nz ? lpg[i] : R(0);
+            dg[i] = i < nz ? lpg[nz + i] : R(0);
+        }
+        const R* Qg = Q + (long long)geom * q_geom_stride;
+        const long long cs = (long long)QX * QY;
+        const int ky1 = t, ky2 = (t == 0) ? LY / 2 : LY - t;
+        const R one = R(1);
+        // input scale: 1/t_l on the sources for the transpose, 1 otherwise
+        auto isc = [&](int l) -> R { return adjoint ? invt[l] : one; };
+        auto osc = [&](int l) -> R { return adjoint ? one : invt[l]; };
+        cpx<R> Ha[3 * NZMAX], Hb[3 * NZMAX];
+        auto store = [&](const cpx<R>* A, int ky) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int l = 0; l < NZMAX; ++l)
+                    if (l < nz) sh[(c * nz + l) * LY + ky] = cscale(A[c * NZMAX + l], osc(l));
+        };
+        if (kx != 0) {
+            auto ina = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky1], isc(l)); };
+            auto inb = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky2], isc(l)); };
+            const R* qrow = Qg + (long long)kx * QY;
+            if (t != 0) mix2<R, NZMAX, true>(nz, ina, inb, Ha, Hb, qrow + t, qrow + t, cs, R(-1), dg);
+            else mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, qrow, qrow + LY / 2, cs, R(1), dg);
+            store(Ha, ky1);
+            store(Hb, ky2);
+        } else {
+            // column 0 holds Z = A + iB with A the kx = 0 and B the kx = Lx/2
+            // column: A(ky) = (Z(ky) + conj Z(-ky))/2, B(ky) = (Z(ky) - conj Z(-ky))/(2i)
+            const R* row0 = Qg;
+            const R* rowM = Qg + (long long)M * QY;
+            if (t != 0) {
+                auto ina = [&](int c, int l) -> cpx<R> {
+                    const cpx<R> z1 = sh[(c * nz + l) * LY + ky1], z2 = sh[(c * nz + l) * LY + ky2];
+                    return cscale(cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}, isc(l));
+                };
+                auto inb = [&](int c, int l) -> cpx<R> {
+                    const cpx<R> z1 = sh[(c * nz + l) * LY + ky1], z2 = sh[(c * nz + l) * LY + ky2];
+                    return cscale(cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)}, isc(l));
+                };
+                mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, row0 + t, rowM + t, cs, R(1), dg);
+                // W(ky) = HA + i HB ; W(-ky) = conj(HA) + i conj(HB)
+#pragma unroll
+                for (int k = 0; k < 3 * NZMAX; ++k) {
+                    const cpx<R> a = Ha[k], bb = Hb[k];
+                    Ha[k] = {a.x - bb.y, a.y + bb.x};
+                    Hb[k] = {a.x + bb.y, bb.x - a.y};
+                }
+                store(Ha, ky1);
+                store(Hb, ky2);
+            } else {
+                // ky = 0 and ky = LY/2 are their own mirror: A = Re Z, B = Im Z
+#pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int kyp = pass == 0 ? 0 : LY / 2;
+                    auto ina = [&](int c, int l) -> cpx<R> {
+                        return {sh[(c * nz + l) * LY + kyp].x * isc(l), R(0)};
+                    };
+                    auto inb = [&](int c, int l) -> cpx<R> {
+                        return {sh[(c * nz + l) * LY + kyp].y * isc(l), R(0)};
+                    };
+                    mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, row0 + kyp, rowM + kyp, cs, R(1), dg);
+#pragma unroll
+                    for (int k = 0; k < 3 * NZMAX; ++k) Ha[k] = {Ha[k].x - Hb[k].y, Ha[k].y + Hb[k].x};
+                    store(Ha, kyp);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int s = grp; s < S; s += NG) {
+        cpx<R>* dst = col + s * sstride;
+        cpx<R>* reg = sh + s * LY;
+        wave_fft<R, LY, true>(
+            reg, g, twy, 1, [&](int pos) -> cpx<R> { return reg[pos]; },
+            [&](int pos, cpx<R> v) {
+                if (pos < ny) dst[pos] = v;
+            });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Five-pass path: y transforms and mixing as separate kernels (any nz).
+// ---------------------------------------------------------------------------
+template <typename R, int LY>
+struct YPassShape {
+    static constexpr int V = fft_vals(LY);
+    static constexpr int GT = LY / V;
+    static constexpr int NG0 = 256 / GT;
+    static constexpr int NGL = (int)(65536 / (sizeof(cpx<R>) * LY));
+    static constexpr int NG = NG0 < NGL ? NG0 : (NGL < 1 ? 1 : NGL);
+    static constexpr int NT = NG * GT;
+};
+
+// columns of n_in complex values (zero padded to LY) -> LY spectrum values
+template <typename R, int LY>
+__global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yfwd(const cpx<R>* __restrict__ in,
+                                                                cpx<R>* __restrict__ out, int n_in,
+                                                                long long ncols,
+                                                                const cpx<R>* __restrict__ twy)
+{
+    using S = YPassShape<R, LY>;
+    __shared__ cpx<R> sh[S::NG * LY];
+    const int tid = threadIdx.x, grp = tid / S::GT, g = tid % S::GT;
+    const long long c = (long long)blockIdx.x * S::NG + grp;
+    if (c >= ncols) return;
+    const cpx<R>* src = in + c * n_in;
+    cpx<R>* dst = out + c * LY;
+    wave_fft<R, LY, false>(
+        sh + grp * LY, g, twy, 1,
+        [&](int pos) -> cpx<R> { return pos < n_in ? src[pos] : cpx<R>{R(0), R(0)}; },
+        [&](int pos, cpx<R> v) { dst[pos] = v; });
+}
+
+// LY spectrum values -> first n_out values of the inverse transform
+template <typename R, int LY>
+__global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yinv(const cpx<R>* __restrict__ in,
+                                                                cpx<R>* __restrict__ out, int n_out,
+                                                                long long ncols,
+                                                                const cpx<R>* __restrict__ twy)
+{
+    using S = YPassShape<R, LY>;
+    __shared__ cpx<R> sh[S::NG * LY];
+    const int tid = threadIdx.x, grp = tid / S::GT, g = tid % S::GT;
+    const long long c = (long long)blockIdx.x * S::NG + grp;
+    if (c >= ncols) return;
+    const cpx<R>* src = in + c * LY;
+    cpx<R>* dst = out + c * n_out;
+    wave_fft<R, LY, true>(
+        sh + grp * LY, g, twy, 1, [&](int pos) -> cpx<R> { return src[pos]; },
+        [&](int pos, cpx<R> v) {
+            if (pos < n_out) dst[pos] = v;
+        });
+}
+
+// Generic z-mixing on full spectra, one thread per (state, kx column, ky).
+template <typename R>
+__global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ Mh,
+                                                     cpx<R>* __restrict__ Hh, int nz, int M, int LY,
+                                                     const R* __restrict__ Q,
+                                                     long long q_geom_stride, int QX, int QY,
+                                                     const R* __restrict__ lp, int bpg, int adjoint)
+{
+    const int ky = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ky >= LY) return;
+    const int kx = blockIdx.y, b = blockIdx.z;
+    const int S = 3 * nz, geom = b / bpg;
+    const long long sst = (long long)M * LY;
+    const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;
+    cpx<R>* hb = Hh + ((long long)b * S * M + kx) * LY;
+    const R* lpg = lp + (long long)geom * 2 * nz;
+    const R* Qg = Q + (long long)geom * q_geom_stride;
+    const long long cs = (long long)QX * QY;
+    const int half = LY / 2;
+    const int kq = ky <= half ? ky : LY - ky;        // quadrant column
+    const R sg = ky <= half ? R(1) : R(-1);          // sign of the ky-odd components
+    const int kyn = (LY - ky) & (LY - 1);            // -ky
+    for (int i = 0; i < nz; ++i) {
+        cpx<R> acc[2][3];
+        for (int p = 0; p < 2; ++p)
+            for (int c = 0; c < 3; ++c) acc[p][c] = {R(0), R(0)};
+        for (int j = 0; j < nz; ++j) {
+            const int a = i < j ? i : j, bq = i < j ? j : i;
+            const int u = a * nz - a * (a - 1) / 2 + (bq - a);
+            const R simag = i <= j ? R(1) : R(-1);     // conj for the transposed pair
+            const R sc = adjoint ? lpg[j] : R(1);
+            const R dgi = (i == j) ? lpg[nz + i] : R(0);
+            const int npts = (kx == 0) ? 2 : 1;
+            for (int p = 0; p < npts; ++p) {
+                const int row = (kx == 0) ? (p == 0 ? 0 : M) : kx;
+                const R* q = Qg + (long long)u * 5 * cs + (long long)row * QY + kq;
+                const R xx = q[0], yy = q[cs], xy = q[2 * cs] * sg, xz = q[3 * cs] * simag,
+                        yz = q[4 * cs] * sg * simag;
+                const R zz = -(xx + yy) + dgi;
+                cpx<R> v[3];
+                for (int c = 0; c < 3; ++c) {
+                    const cpx<R> z1 = mb[(c * nz + j) * sst + ky];
+                    if (kx == 0) {
+                        const cpx<R> z2 = mb[(c * nz + j) * sst + kyn];
+                        v[c] = (p == 0) ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
+                                        : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
+                    } else {
+                        v[c] = z1;
+                    }
+                    v[c] = cscale(v[c], sc);
+                }
+                block_apply(acc[p][0], acc[p][1], acc[p][2], v[0], v[1], v[2], xx, yy, zz, xy, xz, yz);
+            }
+        }
+        const R post = adjoint ? R(1) : lpg[i];
+        for (int c = 0; c < 3; ++c) {
+            cpx<R> w;
+            if (kx == 0) {
+                const cpx<R> A = acc[0][c], B = acc[1][c];
+                w = {A.x - B.y, A.y + B.x};
+            } else {
+                w = acc[0][c];
+            }
+            hb[(c * nz + i) * sst + ky] = cscale(w, post);
+        }
+    }
+}
+
+}  // namespace hfd

@@ -1,0 +1,89 @@
+// Instances of the fused y-pass (y-DFT, z-mixing, inverse y-DFT in LDS).
+#include "field_kernels.hpp"
+#include "launch.hpp"
+
+namespace hfd {
+
+namespace {
+constexpr size_t kMaxFusedLds = 163840;  // 160 KB of LDS per CU on gfx950
+
+template <typename R>
+int nzmax_for(int nz)
+{
+    if (sizeof(R) == 8) return nz <= 4 ? 4 : 0;
+    return nz <= 4 ? 4 : (nz <= 8 ? 8 : (nz <= 12 ? 12 : 0));
+}
+
+template <typename R, int LY, int NZMAX>
+hipError_t fused_t(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
+                   int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
+{
+    const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_ymix_fused<R, LY, NZMAX>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX>), dim3(M, B), dim3(FusedShape<LY>::NT), lds, s,
+                       (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QX, QY, (const R*)lp, bpg, adjoint,
+                       (const cpx<R>*)tw);
+    return hipGetLastError();
+}
+
+template <typename R, int LY>
+hipError_t fused_nz(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
+                    int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
+{
+    switch (nzmax_for<R>(nz)) {
+    case 4: return fused_t<R, LY, 4>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 8:
+        if constexpr (sizeof(R) == 4)
+            return fused_t<R, LY, 8>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+        return hipErrorInvalidValue;
+    case 12:
+        if constexpr (sizeof(R) == 4)
+            return fused_t<R, LY, 12>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t fused_ly(int LY, int nz, void* X, int ny, int M, int B, const void* Q, long long qgs,
+                    int QX, int QY, const void* lp, int bpg, int adjoint, const void* tw,
+                    hipStream_t s)
+{
+    switch (LY) {
+    case 8: return fused_nz<R, 8>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 16: return fused_nz<R, 16>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 32: return fused_nz<R, 32>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 64: return fused_nz<R, 64>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 128: return fused_nz<R, 128>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 256: return fused_nz<R, 256>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 512: return fused_nz<R, 512>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 1024: return fused_nz<R, 1024>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
+{
+    const size_t lds = (fp64 ? 16 : 8) * 3 * (size_t)nz * LY;
+    if (lds_bytes) *lds_bytes = lds;
+    if (LY < 8 || LY > 1024) return false;
+    if ((fp64 ? nzmax_for<double>(nz) : nzmax_for<float>(nz)) == 0) return false;
+    return lds <= kMaxFusedLds;
+}
+
+hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
+                        long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
+                        int adjoint, const void* twy, hipStream_t s)
+{
+    if (!fused_supported(fp64, LY, nz, nullptr)) return hipErrorInvalidValue;
+    if (fp64)
+        return fused_ly<double>(LY, nz, X, ny, M, B, Q, q_geom_stride, QX, QY, lp, bpg, adjoint, twy, s);
+    return fused_ly<float>(LY, nz, X, ny, M, B, Q, q_geom_stride, QX, QY, lp, bpg, adjoint, twy, s);
+}
+
+}  // namespace hfd

@@ -1,0 +1,64 @@
+// Host-side launch wrappers: map run-time sizes onto the compiled template
+// instances.  Each returns hipErrorInvalidValue for a size outside the
+// compiled range (the API layer checks ranges first).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hfd {
+
+constexpr int kMinL = 8;
+constexpr int kMaxL = 4096;
+
+// x pass, forward / inverse (R = float if !fp64 else double)
+hipError_t launch_xfwd(bool fp64, int LX, const void* in, void* out, int nx, int ny,
+                       long long in_sig_stride, int in_row_stride, int nsig, const void* twx,
+                       hipStream_t s);
+hipError_t launch_xinv(bool fp64, int LX, const void* in, void* out, int nx, int ny,
+                       long long out_sig_stride, int out_row_stride, int nsig, const void* twx,
+                       hipStream_t s);
+
+// y pass on columns: forward (n_in values padded to LY) / inverse (first n_out kept)
+hipError_t launch_yfwd(bool fp64, int LY, const void* in, void* out, int n_in, long long ncols,
+                       const void* twy, hipStream_t s);
+hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, long long ncols,
+                       const void* twy, hipStream_t s);
+
+// fused y pass: does a compiled instance exist for (fp64, LY, nz) with lds bytes?
+bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes);
+hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
+                        long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
+                        int adjoint, const void* twy, hipStream_t s);
+
+hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
+                              const void* Q, long long q_geom_stride, int QX, int QY, const void* lp,
+                              int bpg, int adjoint, hipStream_t s);
+
+// split-BF16 MFMA mixing on full spectra (FP32 path only)
+hipError_t launch_mix_bf16(const void* Mh, void* Hh, int nz, int M, int LY, int B, const void* Qs,
+                           long long qs_geom_stride, int QX, int QY, const void* lp, int bpg,
+                           int adjoint, hipStream_t s);
+// three-way BF16 split of an FP32 tensor into the MFMA operand layout
+hipError_t launch_split_tensor(const float* Q, void* Qs, int G, int nz, int QX, int QY,
+                               const float* lp, int Lxy_unused, hipStream_t s);
+long long split_tensor_bytes(int G, int nz, int QX, int QY);
+
+// thickness-gradient reduction over the spectra
+hipError_t launch_tgrad_reduce(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY,
+                               int B, const void* Q, long long q_geom_stride, const float* D,
+                               long long d_geom_stride, const int* zidx, const void* lp, int bpg,
+                               int QX, int QY, double* partial, int nblk_x, hipStream_t s);
+hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const void* lp,
+                               bool fp64, int bpg, double* grad_t, hipStream_t s);
+
+// tensor setup (FP64)
+struct PairGeoH {
+    double ti, tj, Z, pad;
+};
+hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
+                              int Ly, double dx, double dy, int mode, hipStream_t s);
+hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
+                               int Ly, double dx, double dy, hipStream_t s);
+hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
+                       int comps, int M, int Ly, int QX, int QY, hipStream_t s);
+
+}  // namespace hfd

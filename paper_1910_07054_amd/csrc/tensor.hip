@@ -1,0 +1,46 @@
+// Instances of the FP64 tensor-setup kernels.
+#include "launch.hpp"
+#include "tensor_kernels.hpp"
+
+namespace hfd {
+
+static_assert(sizeof(PairGeo) == sizeof(PairGeoH), "pair record layout");
+
+hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
+                              int Ly, double dx, double dy, int mode, hipStream_t s)
+{
+    const long long n = (long long)nx * ny * npairs;
+    const long long nb = (n + 127) / 128;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tensor_real, dim3((unsigned)nb), dim3(128), 0, s, W, (const PairGeo*)pg,
+                       npairs, nx, ny, Lx, Ly, dx, dy, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
+                               int Ly, double dx, double dy, hipStream_t s)
+{
+    const long long n = (long long)nx * ny * nzeta;
+    const long long nb = (n + 127) / 128;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dtensor_real, dim3((unsigned)nb), dim3(128), 0, s, W, zeta, nzeta, nx, ny,
+                       Lx, Ly, dx, dy);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
+                       int comps, int M, int Ly, int QX, int QY, hipStream_t s)
+{
+    const long long n = (long long)npairs * comps * QX * QY;
+    const long long nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (out_fp64)
+        hipLaunchKernelGGL(k_pack<double>, dim3((unsigned)nb), dim3(256), 0, s,
+                           (const cpx<double>*)F, (double*)Q, scale, npairs, comps, M, Ly, QX, QY);
+    else
+        hipLaunchKernelGGL(k_pack<float>, dim3((unsigned)nb), dim3(256), 0, s,
+                           (const cpx<double>*)F, (float*)Q, scale, npairs, comps, M, Ly, QX, QY);
+    return hipGetLastError();
+}
+
+}  // namespace hfd

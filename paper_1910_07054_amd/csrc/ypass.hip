@@ -1,0 +1,76 @@
+// Instances of the y-pass column kernels and of the generic z-mixing kernel.
+#include "field_kernels.hpp"
+#include "launch.hpp"
+
+namespace hfd {
+
+template <typename R, int LY>
+static hipError_t yfwd_t(const void* in, void* out, int n, long long ncols, const void* tw,
+                         hipStream_t s)
+{
+    using S = YPassShape<R, LY>;
+    const long long nb = (ncols + S::NG - 1) / S::NG;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_yfwd<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<R>*)in,
+                       (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    return hipGetLastError();
+}
+
+template <typename R, int LY>
+static hipError_t yinv_t(const void* in, void* out, int n, long long ncols, const void* tw,
+                         hipStream_t s)
+{
+    using S = YPassShape<R, LY>;
+    const long long nb = (ncols + S::NG - 1) / S::NG;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_yinv<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<R>*)in,
+                       (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    return hipGetLastError();
+}
+
+#define HFD_Y_CASES(F, R, ...)                         \
+    switch (LY) {                                      \
+    case 8: return F<R, 8>(__VA_ARGS__);               \
+    case 16: return F<R, 16>(__VA_ARGS__);             \
+    case 32: return F<R, 32>(__VA_ARGS__);             \
+    case 64: return F<R, 64>(__VA_ARGS__);             \
+    case 128: return F<R, 128>(__VA_ARGS__);           \
+    case 256: return F<R, 256>(__VA_ARGS__);           \
+    case 512: return F<R, 512>(__VA_ARGS__);           \
+    case 1024: return F<R, 1024>(__VA_ARGS__);         \
+    case 2048: return F<R, 2048>(__VA_ARGS__);         \
+    case 4096: return F<R, 4096>(__VA_ARGS__);         \
+    default: return hipErrorInvalidValue;              \
+    }
+
+hipError_t launch_yfwd(bool fp64, int LY, const void* in, void* out, int n_in, long long ncols,
+                       const void* twy, hipStream_t s)
+{
+    if (fp64) { HFD_Y_CASES(yfwd_t, double, in, out, n_in, ncols, twy, s) }
+    HFD_Y_CASES(yfwd_t, float, in, out, n_in, ncols, twy, s)
+}
+
+hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, long long ncols,
+                       const void* twy, hipStream_t s)
+{
+    if (fp64) { HFD_Y_CASES(yinv_t, double, in, out, n_out, ncols, twy, s) }
+    HFD_Y_CASES(yinv_t, float, in, out, n_out, ncols, twy, s)
+}
+
+hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
+                              const void* Q, long long qgs, int QX, int QY, const void* lp,
+                              int bpg, int adjoint, hipStream_t s)
+{
+    dim3 grid((LY + 255) / 256, M, B);
+    if (fp64)
+        hipLaunchKernelGGL(k_mix_generic<double>, grid, dim3(256), 0, s, (const cpx<double>*)Mh,
+                           (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs, QX, QY,
+                           (const double*)lp, bpg, adjoint);
+    else
+        hipLaunchKernelGGL(k_mix_generic<float>, grid, dim3(256), 0, s, (const cpx<float>*)Mh,
+                           (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QX, QY,
+                           (const float*)lp, bpg, adjoint);
+    return hipGetLastError();
+}
+
+}  // namespace hfd

@@ -1,0 +1,265 @@
+"""Python binding of the HIP library ``libhfd.so`` (C ABI in include/hfd.h).
+
+Argument marshalling only: every step of the field computation runs in the
+library's kernels.  PyTorch supplies device memory (``tensor.data_ptr()``) and
+the current HIP stream.  If the library has not been built the first call
+raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfd.so")
+
+HFD_OK, HFD_EINVAL, HFD_ENOMEM, HFD_EHIP, HFD_EBATCH, HFD_EHANDLE, HFD_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+HFD_FP32, HFD_FP64, HFD_MIX_SPLIT_BF16, HFD_SPLIT_PASSES, HFD_STORE_DTENSOR = 0, 1, 2, 4, 8
+
+STATUS_NAMES = {0: "HFD_OK", -1: "HFD_EINVAL", -2: "HFD_ENOMEM", -3: "HFD_EHIP", -4: "HFD_EBATCH",
+                -5: "HFD_EHANDLE", -6: "HFD_ENOTSUP"}
+
+# every function declared in include/hfd.h
+EXPORTS = (
+    "hfd_setup_tensor", "hfd_set_thickness", "hfd_demag_field", "hfd_demag_vjp", "hfd_time_stages",
+    "hfd_autotune", "hfd_get_info", "hfd_export_fourier_tensor", "hfd_export_real_tensor",
+    "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error",
+)
+
+
+class HFDError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("n_geom", ctypes.c_int), ("batch_max", ctypes.c_int), ("Lx", ctypes.c_int),
+                ("Ly", ctypes.c_int), ("fused", ctypes.c_int), ("fp64", ctypes.c_int),
+                ("mix_bf16", ctypes.c_int), ("tensor_bytes", ctypes.c_longlong),
+                ("work_bytes", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhfd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build the HIP library first "
+                           "(python -m paper_1910_07054_amd.build)")
+    lib = ctypes.CDLL(path)
+    i, d, p, ll = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
+    sig = {
+        "hfd_setup_tensor": [ctypes.POINTER(p), i, i, d, d, i, p, p, i, i, ctypes.c_uint, p],
+        "hfd_set_thickness": [p, p, p, p],
+        "hfd_demag_field": [p, p, p, i, p],
+        "hfd_demag_vjp": [p, p, p, p, p, i, p],
+        "hfd_time_stages": [p, p, p, i, i, p, p, p, p, i],
+        "hfd_autotune": [p, i, p, p, i],
+        "hfd_get_info": [p, ctypes.POINTER(Info)],
+        "hfd_export_fourier_tensor": [p, i, p, ll],
+        "hfd_export_real_tensor": [p, i, i, i, p, p],
+        "hfd_forward_spectrum": [p, p, p, ll, i, p],
+        "hfd_destroy": [p],
+        "hfd_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "hfd_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != HFD_OK:
+        msg = load().hfd_last_error()
+        raise HFDError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Plan:
+    """A geometry (nx, ny, dx, dy and one or more layer stacks) with its Fourier
+    tensor on the GPU.  ``thickness`` and ``z_bottom`` are [nz] or [n_geom][nz]
+    host arrays (z_bottom None stacks the layers without gaps)."""
+
+    def __init__(self, nx: int, ny: int, dx: float, dy: float, thickness, z_bottom=None,
+                 batch_max: int = 1, flags: int = HFD_FP32, stream=None):
+        lib = load()
+        t = np.ascontiguousarray(np.atleast_2d(np.asarray(thickness, dtype=np.float64)))
+        z = None if z_bottom is None else np.ascontiguousarray(
+            np.atleast_2d(np.asarray(z_bottom, dtype=np.float64)))
+        if z is not None and z.shape != t.shape:
+            raise ValueError("z_bottom must have the shape of thickness")
+        self.n_geom, self.nz = t.shape
+        self.nx, self.ny, self.dx, self.dy = int(nx), int(ny), float(dx), float(dy)
+        self.flags = int(flags)
+        self.batch_max = int(batch_max)
+        self.thickness = t.copy()
+        self.z_bottom = None if z is None else z.copy()
+        h = ctypes.c_void_p()
+        _check(lib.hfd_setup_tensor(ctypes.byref(h), self.nx, self.ny, self.dx, self.dy, self.nz,
+                                    t.ctypes.data, None if z is None else z.ctypes.data,
+                                    self.n_geom, self.batch_max, self.flags,
+                                    _stream_handle(stream)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    @property
+    def fp64(self) -> bool:
+        return bool(self.flags & HFD_FP64)
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(load().hfd_get_info(self.handle, ctypes.byref(inf)))
+        return inf
+
+    def set_thickness(self, thickness, z_bottom=None, stream=None):
+        t = np.ascontiguousarray(np.atleast_2d(np.asarray(thickness, dtype=np.float64)))
+        z = None if z_bottom is None else np.ascontiguousarray(
+            np.atleast_2d(np.asarray(z_bottom, dtype=np.float64)))
+        _check(load().hfd_set_thickness(self.handle, t.ctypes.data,
+                                        None if z is None else z.ctypes.data,
+                                        _stream_handle(stream)))
+        self.thickness = t.copy()
+        self.z_bottom = None if z is None else z.copy()
+
+    # -- field ---------------------------------------------------------------
+    def field(self, m, out=None, stream=None):
+        """h = -N * m for m of shape [B, 3, nz, ny, nx] (torch, on the GPU)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(m)
+        B = m.shape[0]
+        _check(load().hfd_demag_field(self.handle, _dptr(m), _dptr(out), int(B),
+                                      _stream_handle(stream)))
+        return out
+
+    def vjp(self, m, grad_h, want_m: bool = True, want_t: bool = True, stream=None):
+        """(grad_m, grad_thickness[B, nz] float64) of <grad_h, h(m, t)>."""
+        import torch
+        B = grad_h.shape[0]
+        gm = torch.empty_like(grad_h) if want_m else None
+        gt = torch.empty((B, self.nz), dtype=torch.float64, device=grad_h.device) if want_t else None
+        _check(load().hfd_demag_vjp(self.handle, _dptr(m) if m is not None else None, _dptr(grad_h),
+                                    _dptr(gm) if gm is not None else None,
+                                    _dptr(gt) if gt is not None else None, int(B),
+                                    _stream_handle(stream)))
+        return gm, gt
+
+    def forward_spectrum(self, m, stream=None):
+        import torch
+        inf = self.info()
+        B = m.shape[0]
+        dt = torch.complex128 if self.fp64 else torch.complex64
+        out = torch.empty((B, 3, self.nz, inf.Lx // 2, inf.Ly), dtype=dt, device=m.device)
+        _check(load().hfd_forward_spectrum(self.handle, _dptr(m), _dptr(out),
+                                           out.numel() * out.element_size(), int(B),
+                                           _stream_handle(stream)))
+        return out
+
+    def time_stages(self, m, h, reps: int = 20, stream=None):
+        ms = (ctypes.c_double * 8)()
+        n = ctypes.c_int()
+        names = ctypes.create_string_buffer(256)
+        _check(load().hfd_time_stages(self.handle, _dptr(m), _dptr(h), int(m.shape[0]), int(reps),
+                                      _stream_handle(stream), ms, ctypes.byref(n), names, 256))
+        labels = names.value.decode().split(";")
+        return {labels[k]: ms[k] for k in range(n.value)}
+
+    def autotune(self, batch: int = 1, stream=None) -> str:
+        rep = ctypes.create_string_buffer(1024)
+        _check(load().hfd_autotune(self.handle, int(batch), _stream_handle(stream), rep, 1024))
+        return rep.value.decode()
+
+    # -- inspection ----------------------------------------------------------
+    def export_fourier_tensor(self, geom: int = 0) -> np.ndarray:
+        inf = self.info()
+        P = self.nz * (self.nz + 1) // 2
+        QX, QY = inf.Lx // 2 + 1, inf.Ly // 2 + 1
+        out = np.empty((P, 5, QX, QY), dtype=np.float64 if self.fp64 else np.float32)
+        _check(load().hfd_export_fourier_tensor(self.handle, int(geom), out.ctypes.data, out.nbytes))
+        return out
+
+    def export_real_tensor(self, i: int, j: int, geom: int = 0, stream=None) -> np.ndarray:
+        out = np.empty((6, 2 * self.ny - 1, 2 * self.nx - 1), dtype=np.float64)
+        _check(load().hfd_export_real_tensor(self.handle, int(geom), int(i), int(j), out.ctypes.data,
+                                             _stream_handle(stream)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _check(load().hfd_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _autograd():
+    import torch
+
+    class DemagField(torch.autograd.Function):
+        """h = -N(t) * m with gradients for m and for the layer thicknesses.
+
+        forward(m, thickness, plan): ``thickness`` must equal the plan's
+        thicknesses ([n_geom, nz] float64 tensor); the backward pass returns
+        d/dm through the transposed field kernel and d/dthickness through the
+        thickness derivative of the Newell tensor (layers above a thickened
+        layer move up, gaps fixed)."""
+
+        @staticmethod
+        def forward(ctx, m, thickness, plan):
+            tt = thickness.detach().cpu().numpy().reshape(plan.n_geom, plan.nz)
+            if not np.array_equal(tt, plan.thickness):
+                raise ValueError("thickness differs from the plan geometry; call plan.set_thickness")
+            ctx.plan = plan
+            ctx.save_for_backward(m)
+            return plan.field(m)
+
+        @staticmethod
+        def backward(ctx, grad_h):
+            (m,) = ctx.saved_tensors
+            plan = ctx.plan
+            need_m, need_t = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            gm, gt = plan.vjp(m, grad_h.contiguous(), want_m=need_m, want_t=need_t)
+            gthick = None
+            if need_t:
+                B = gt.shape[0]
+                gthick = gt.reshape(plan.n_geom, B // plan.n_geom, plan.nz).sum(1)
+            return gm, gthick, None
+
+    return DemagField
+
+
+def demag_field(m, thickness, plan: Plan):
+    """Differentiable h = -N(thickness) * m (see DemagField)."""
+    return _autograd().apply(m, thickness, plan)

@@ -1,0 +1,51 @@
+"""Shared helpers for the GPU parity tests (not a test module)."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_1910_07054_amd import hfd
+
+
+def rel_err(got: np.ndarray, ref: np.ndarray) -> float:
+    """max |got - ref| over cells and components divided by the largest field
+    magnitude |ref|_2 over cells (component axis = -4 for [..][3][nz][ny][nx],
+    or the last axis for [S][3] samples)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if ref.ndim == 2 and ref.shape[-1] == 3:
+        norm = np.sqrt((ref ** 2).sum(-1)).max()
+    else:
+        norm = np.sqrt((ref ** 2).sum(-4)).max()
+    return float(np.abs(got - ref).max() / norm)
+
+
+def plan_for(wl, flags=hfd.HFD_FP32, batch_max=None):
+    return hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom,
+                    batch_max=batch_max or wl.batch, flags=flags)
+
+
+def run_field(plan, m_np, stream=None):
+    """m_np: [B][3][nz][ny][nx] float64 -> (h float64, m as rounded to the
+    plan precision in float64)."""
+    import torch
+    dt = np.float64 if plan.fp64 else np.float32
+    mm = np.ascontiguousarray(m_np.astype(dt))
+    m = torch.from_numpy(mm).cuda()
+    h = plan.field(m)
+    torch.cuda.synchronize()
+    return h.cpu().numpy().astype(np.float64), mm.astype(np.float64)
+
+
+def expected_quadrant(Ntil: np.ndarray, thick: np.ndarray, Lx: int, Ly: int) -> np.ndarray:
+    """Stored-tensor convention from the oracle's DFT of the pair tables:
+    [P][5][Lx/2+1][Ly/2+1] with (xx, yy, xy) real and (xz, yz) imaginary parts
+    of t_i * (-Ntil / (Lx Ly)), unique pairs i <= j."""
+    nz = Ntil.shape[0]
+    QX, QY = Lx // 2 + 1, Ly // 2 + 1
+    out = []
+    for i in range(nz):
+        for j in range(i, nz):
+            T = thick[i] * (-Ntil[i, j] / (Lx * Ly))          # [6][Ly][Lx]
+            q = T[:, :QY, :QX].transpose(0, 2, 1)               # [6][QX][QY]
+            out.append(np.stack([q[0].real, q[1].real, q[3].real, q[4].imag, q[5].imag]))
+    return np.array(out)

@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/hfd.h, and rejects invalid arguments on the host before
+any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_07054_amd import hfd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hfd.h")
+
+
+def _lib():
+    if not os.path.exists(hfd.LIB_PATH):
+        from paper_1910_07054_amd import build
+        build.build()
+    return hfd.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hfd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding():
+    assert sorted(hfd.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _setup(**kw):
+    lib = _lib()
+    args = dict(nx=8, ny=8, dx=1.0, dy=1.0, nz=2, thickness=np.array([1.0, 1.0]), z_bottom=None,
+                n_geom=1, batch_max=1, flags=0)
+    args.update(kw)
+    t = np.ascontiguousarray(args["thickness"], dtype=np.float64)
+    z = args["z_bottom"]
+    z = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = lib.hfd_setup_tensor(ctypes.byref(h), args["nx"], args["ny"], args["dx"], args["dy"],
+                              args["nz"], t.ctypes.data, None if z is None else z.ctypes.data,
+                              args["n_geom"], args["batch_max"], args["flags"], None)
+    return st, lib.hfd_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(nx=0), "nx and ny"),
+    (dict(ny=4097), "nx and ny"),
+    (dict(dx=0.0), "dx and dy"),
+    (dict(dy=float("nan")), "dx and dy"),
+    (dict(nz=0, thickness=np.zeros(1)), "nz"),
+    (dict(nz=65, thickness=np.ones(65)), "nz"),
+    (dict(thickness=np.array([1.0, -0.5])), "thickness"),
+    (dict(thickness=np.array([1.0, np.inf])), "thickness"),
+    (dict(z_bottom=np.array([0.0, 0.5])), "overlap"),
+    (dict(z_bottom=np.array([0.0, np.nan])), "z_bottom"),
+    (dict(z_bottom=np.array([2.0, 0.0])), "overlap"),
+    (dict(n_geom=0), "n_geom"),
+    (dict(batch_max=0), "batch_max"),
+    (dict(n_geom=2, batch_max=1, thickness=np.ones(4)), "batch_max"),
+    (dict(flags=1 << 10), "flag"),
+    (dict(flags=hfd.HFD_FP64 | hfd.HFD_MIX_SPLIT_BF16), "BF16"),
+])
+def test_setup_rejects_invalid_arguments(kw, frag):
+    st, msg = _setup(**kw)
+    assert st == hfd.HFD_EINVAL
+    assert frag.lower() in msg.lower()
+
+
+def test_null_and_unknown_handles_rejected():
+    lib = _lib()
+    assert lib.hfd_demag_field(None, 16, 16, 1, None) == hfd.HFD_EHANDLE
+    assert lib.hfd_destroy(None) == hfd.HFD_EHANDLE
+    bogus = ctypes.c_void_p(0x1000)
+    assert lib.hfd_demag_field(bogus, 16, 16, 1, None) == hfd.HFD_EHANDLE
+    assert "destroyed" in lib.hfd_last_error().decode() or "never" in lib.hfd_last_error().decode()
+    assert lib.hfd_demag_vjp(None, None, None, None, None, 1, None) == hfd.HFD_EHANDLE
+    assert lib.hfd_get_info(None, None) == hfd.HFD_EHANDLE
+    assert lib.hfd_setup_tensor(None, 8, 8, 1.0, 1.0, 1, None, None, 1, 1, 0, None) == hfd.HFD_EINVAL
+
+
+def test_touching_layers_accepted_by_validation():
+    """Layers that touch (z_bottom[l+1] == top of l, up to rounding) pass the
+    host validation; the failure, if any, then comes from the device (no GPU
+    here), not from the geometry check."""
+    t = np.array([0.7, 1.3, 0.4])
+    z = np.cumsum(np.concatenate([[0.0], t[:-1]]))
+    st, msg = _setup(nz=3, thickness=t, z_bottom=z)
+    assert "overlap" not in msg.lower()

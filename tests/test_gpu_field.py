@@ -1,0 +1,143 @@
+"""GPU parity of the field path against the oracle (element by element)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_07054_amd import hfd
+from paper_1910_07054_amd import workloads as W
+from hfd_testlib import expected_quadrant, plan_for, rel_err, run_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hfd.load()
+
+
+# ---------------------------------------------------------------------------
+# Tensor setup: real space (Newell near field + quadrature far field) and the
+# packed Fourier tensor
+# ---------------------------------------------------------------------------
+def test_real_tensor_matches_oracle_near_and_far():
+    wl = W.small_case(40, 33, 3, seed=101, dx=2.5, dy=2.0)
+    plan = plan_for(wl)
+    t, zb = wl.thickness[0], wl.z_bottom[0]
+    for (i, j) in [(0, 0), (0, 2), (2, 0), (1, 2), (2, 2)]:
+        got = plan.export_real_tensor(i, j)
+        ref = oracle.pair_table(wl.nx, wl.ny, wl.dx, wl.dy, zb[i], zb[i] + t[i], zb[j], zb[j] + t[j])
+        scale = np.abs(ref).max()
+        diff = np.abs(got - ref)
+        # near field ~1e-9 relative (FP64 Newell), far field quadrature ~1e-11
+        assert diff.max() < 2e-9 * scale, (i, j, diff.max() / scale)
+        assert np.all(diff <= 1e-8 * np.abs(ref) + 1e-12 * scale), (i, j)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_fourier_tensor_matches_oracle(fp64):
+    wl = W.small_case(12, 9, 3, seed=102)
+    plan = plan_for(wl, flags=hfd.HFD_FP64 if fp64 else hfd.HFD_FP32)
+    inf = plan.info()
+    t, zb = wl.thickness[0], wl.z_bottom[0]
+    Nt = oracle.fourier_tensor(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, Lx=inf.Lx, Ly=inf.Ly)
+    ref = expected_quadrant(Nt, t, inf.Lx, inf.Ly)
+    got = plan.export_fourier_tensor().astype(np.float64)
+    scale = np.abs(ref).max()
+    tol = 1e-12 if fp64 else 2e-7
+    assert np.abs(got - ref).max() < tol * scale
+    # zz from the trace: t_i T_zz = [i == j](-t_i/(Lx Ly)) - xx - yy
+    u = 0
+    for i in range(3):
+        for j in range(i, 3):
+            Tzz = (t[i] * (-Nt[i, j, 2] / (inf.Lx * inf.Ly))).real[: inf.Ly // 2 + 1, : inf.Lx // 2 + 1].T
+            zz = -(got[u, 0] + got[u, 1]) + (-t[i] / (inf.Lx * inf.Ly) if i == j else 0.0)
+            assert np.abs(zz - Tzz).max() < tol * scale * 4
+            u += 1
+    plan.destroy()
+
+
+# ---------------------------------------------------------------------------
+# Forward 2D transform of the zero-padded magnetization
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fp64", [False, True])
+def test_forward_spectrum_matches_numpy(fp64):
+    import torch
+    wl = W.small_case(21, 10, 2, seed=103, batch=2)
+    plan = plan_for(wl, flags=hfd.HFD_FP64 if fp64 else hfd.HFD_FP32)
+    inf = plan.info()
+    dt = np.float64 if fp64 else np.float32
+    mm = wl.m.astype(dt)
+    got = plan.forward_spectrum(torch.from_numpy(mm).cuda()).cpu().numpy()
+    X = np.fft.fft2(mm.astype(np.float64), s=(inf.Ly, inf.Lx))      # [B][3][nz][Ly][Lx]
+    M = inf.Lx // 2
+    ref = np.empty(got.shape, dtype=np.complex128)
+    ref[..., 1:, :] = np.swapaxes(X[..., :, 1:M], -1, -2)
+    # column 0 packs kx = 0 and kx = Lx/2: y-DFT of (X_x(0) + i X_x(M)) per row
+    Xx = np.fft.fft(mm.astype(np.float64), n=inf.Lx, axis=-1)          # x transform only
+    packed = Xx[..., 0].real + 1j * Xx[..., M].real                   # [B][3][nz][ny]
+    ref[..., 0, :] = np.fft.fft(packed, n=inf.Ly, axis=-1)
+    scale = np.abs(ref).max()
+    tol = 1e-13 if fp64 else 1e-6
+    assert np.abs(got - ref).max() < tol * scale
+    plan.destroy()
+
+
+# ---------------------------------------------------------------------------
+# Field against the brute-force oracle
+# ---------------------------------------------------------------------------
+SMALL = [
+    # (nx, ny, nz, seed, batch): ragged sizes, several tiles, touching layers
+    (16, 16, 3, 201, 1),
+    (37, 23, 4, 202, 2),
+    (64, 48, 5, 203, 1),
+    (30, 70, 2, 204, 3),
+    (1, 9, 3, 205, 1),
+    (11, 1, 2, 206, 1),
+    (5, 5, 1, 207, 1),
+    (24, 20, 9, 208, 1),
+]
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "x".join(map(str, c[:3])))
+def test_field_matches_bruteforce(case, fp64, split):
+    nx, ny, nz, seed, B = case
+    wl = W.small_case(nx, ny, nz, seed=seed, batch=B)
+    flags = (hfd.HFD_FP64 if fp64 else hfd.HFD_FP32) | (hfd.HFD_SPLIT_PASSES if split else 0)
+    plan = plan_for(wl, flags=flags)
+    h, mused = run_field(plan, wl.m)
+    for b in range(B):
+        ref = oracle.field(nx, ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
+        err = rel_err(h[b], ref)
+        assert err < (1e-11 if fp64 else 1e-5), (b, err)
+    plan.destroy()
+
+
+def test_c1_fp64_matches_bruteforce():
+    wl = W.c1()
+    plan = plan_for(wl, flags=hfd.HFD_FP64)
+    h, mused = run_field(plan, wl.m)
+    ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[0])
+    assert rel_err(h[0], ref) < 1e-10
+    plan.destroy()
+
+
+def test_adjoint_matches_oracle_transpose():
+    import torch
+    for fp64 in (False, True):
+        wl = W.small_case(19, 13, 4, seed=301, batch=2)
+        plan = plan_for(wl, flags=hfd.HFD_FP64 if fp64 else hfd.HFD_FP32)
+        dt = np.float64 if fp64 else np.float32
+        g = np.random.default_rng(5).standard_normal(wl.m.shape).astype(dt)
+        gm, _ = plan.vjp(None, torch.from_numpy(g).cuda(), want_m=True, want_t=False)
+        gm = gm.cpu().numpy().astype(np.float64)
+        for b in range(2):
+            ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0],
+                               g[b].astype(np.float64), transpose=True)
+            assert rel_err(gm[b], ref) < (1e-11 if fp64 else 1e-5)
+        plan.destroy()
