@@ -1,0 +1,212 @@
+"""Throughput benchmark of the hybrid-FFT demagnetization field on one MI355X.
+
+One step = one full field evaluation h = -N * m (x-pass R2C, y-pass with the
+explicit z-mixing, inverse x-pass) of the 256 x 256 x 8 MRAM-like stack
+(2.5 nm cells, FP32 field, tensor set up in FP64 beforehand), inputs resident
+in HBM.  Steps are replayed from a HIP graph.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, public spec
+FP32_VALU_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="M0")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--split", action="store_true", help="force the five-pass path")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(nx, ny, nz, B, Lx, Ly):
+    """m in + h out (FP32) + the unique-pair Fourier tensor (5 FP32 components on
+    the (Lx/2+1) x (Ly/2+1) quadrant) read once."""
+    P = nz * (nz + 1) // 2
+    return B * 24 * nx * ny * nz + P * 5 * (Lx // 2 + 1) * (Ly // 2 + 1) * 4
+
+
+def fused_kernel_bytes(nx, ny, nz, B, Lx, Ly):
+    """Bytes the fused y-pass kernel must move: the x-pass spectra in and out
+    (complex64, Lx/2 columns of ny) plus the tensor quadrant."""
+    P = nz * (nz + 1) // 2
+    return 2 * B * 3 * nz * (Lx // 2) * ny * 8 + P * 5 * (Lx // 2 + 1) * (Ly // 2 + 1) * 4
+
+
+def cpu_baseline(wl, target_s=12.0):
+    """The oracle's brute-force sum timed on a bounded sample of target cells of
+    layer 0 (all sources of all layers), extrapolated to one full evaluation.
+    Pair-table construction (the oracle's tensor setup) is timed apart and not
+    counted, as the GPU figure excludes the tensor setup."""
+    import oracle
+    zb, t = wl.z_bottom[0], wl.thickness[0]
+    m = wl.m[0].astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(7)
+
+    def samples(n):
+        ys = rng.integers(0, wl.ny, n)
+        xs = rng.integers(0, wl.nx, n)
+        return np.stack([np.zeros(n, dtype=np.int64), ys, xs], 1)
+
+    t0 = time.perf_counter()
+    oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, samples=samples(1))
+    t_tab = time.perf_counter() - t0
+    n = 64
+    t0 = time.perf_counter()
+    oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, samples=samples(n))
+    t_n = time.perf_counter() - t0
+    per = max((t_n - t_tab) / n, 1e-9)
+    n2 = int(min(4096, max(n, target_s / per)))
+    t0 = time.perf_counter()
+    oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, samples=samples(n2))
+    t_n2 = time.perf_counter() - t0
+    per = max((t_n2 - t_tab) / n2, 1e-12)
+    cells = wl.nx * wl.ny * wl.nz
+    t_eval = per * cells
+    return {
+        "value": 1.0 / t_eval,
+        "unit": "evals/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"brute-force FP64 sum (extended-precision tensor tables) for {n2} random target "
+                   f"cells of layer 0 against all {cells} source cells, {t_n2:.1f} s incl. "
+                   f"{t_tab:.1f} s of pair tables for that layer; extrapolated to {cells} targets "
+                   f"= {t_eval:.0f} s per evaluation (tables excluded)"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the method needs no inter-GPU "
+              "exchange for a single field evaluation at this size); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_07054_amd import hfd
+    from paper_1910_07054_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    hfd.load()
+    wl = W.CONFIGS[args.workload]()
+    dev = torch.device("cuda:0")
+    B = wl.batch
+    flags = hfd.HFD_FP32 | (hfd.HFD_SPLIT_PASSES if args.split else 0)
+    t0 = time.perf_counter()
+    plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=B, flags=flags)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    inf = plan.info()
+    m = torch.from_numpy(wl.m.astype(np.float32)).to(dev)
+    h = torch.empty_like(m)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    with torch.cuda.stream(stream):
+        for _ in range(max(args.warmup, 1)):
+            plan.field(m, out=h, stream=stream)
+    torch.cuda.synchronize()
+
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            plan.field(m, out=h, stream=stream)
+        for _ in range(3):
+            graph.replay()
+        torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            if graph is not None:
+                graph.replay()
+            else:
+                plan.field(m, out=h, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    evals_per_s = B / (elapsed / args.steps)
+
+    # per-stage kernel durations with HIP events on the launch stream
+    stages = plan.time_stages(m, h, reps=max(args.steps, 10), stream=stream)
+    torch.cuda.synchronize()
+    dom = max(stages, key=stages.get)
+    if dom == "ymix_fused":
+        dom_bytes = fused_kernel_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly)
+    else:
+        dom_bytes = None
+    alg_bytes = algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly)
+
+    # accuracy against stored oracle values for this workload, if present
+    err = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{wl.name}_samples.npz")
+    if os.path.exists(gpath):
+        g = np.load(gpath)
+        s = g["samples"]
+        hh = h.cpu().numpy()
+        got = hh[g["state"], :, s[:, 0], s[:, 1], s[:, 2]]
+        ref = g["h"]
+        err = float(np.abs(got - ref).max() / g["hnorm_max"])
+
+    roof = None
+    if dom_bytes is not None:
+        achieved = dom_bytes / (stages[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": dom,
+                "kernel_ms": stages[dom], "kernel_alg_bytes": dom_bytes}
+
+    out = {
+        "metric": "demag field evals/s at 256^2 x 8 layers",
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.nx}x{wl.ny} cells of {wl.dx} nm, {wl.nz} layers "
+                               f"(MRAM-like stack, seed {wl.seed}), batch {B}, FP32 field / FP64 tensor",
+                   "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "batch": B, "Lx": inf.Lx, "Ly": inf.Ly,
+                   "path": "fused" if inf.fused else "split", "graph": graph is not None},
+        "cell_updates_per_s": evals_per_s * wl.nx * wl.ny * wl.nz,
+        "alg_GBps": alg_bytes / (elapsed / args.steps) / 1e9,
+        "alg_bytes_per_eval": alg_bytes,
+        "err_vs_fp64_oracle": err,
+        "stage_ms": stages,
+        "setup_ms": setup_ms,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -481,6 +481,16 @@ int hfdo_thickness_grad(int nx, int ny, int nz, double dx, double dy, const doub
     double *box = (mode == 1) ? (double *)malloc(sizeof(double) * (size_t)(Wo + 1) * (Ho + 1)) : NULL;
     if (!dt || !gb || !gtp || (mode == 1 && !box)) { free(dt); free(gb); free(gtp); free(box); return -2; }
     for (int i = 0; i < nz; ++i) {
+        /* a target layer whose upstream gradient is zero contributes nothing */
+        int gzero = 1;
+        if (mode == 1) {
+            for (int r = 0; r < 3; ++r) if (g[3 * (size_t)i + r] != 0.0) gzero = 0;
+        } else {
+            for (int r = 0; r < 3 && gzero; ++r)
+                for (size_t c = 0; c < cells; ++c)
+                    if (g[(size_t)r * cs + (size_t)i * cells + c] != 0.0) { gzero = 0; break; }
+        }
+        if (gzero) continue;
         for (int j = 0; j < nz; ++j) {
             int rc = hfdo_pair_dtable(nx, ny, dx, dy, zbot[i], zbot[i] + thick[i], zbot[j],
                                       zbot[j] + thick[j], dt);

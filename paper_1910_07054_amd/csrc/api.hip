@@ -106,15 +106,22 @@ struct hfd_plan_s {
     void* Hh = nullptr;
     size_t x1_bytes = 0, mh_bytes = 0;
     // thickness-derivative data
-    float* D = nullptr;         // [G][nzeta_max][6][QX][QY]
-    long long d_geom_stride = 0;
-    int* zidx = nullptr;        // [G][nz][nz][4]
+    void* D = nullptr;          // [G or 1][nzeta_max][6][QX][QY] plan precision
+    long long d_geom_stride = 0;  // elements per geometry
+    int d_geoms = 0;            // geometries D holds (G when stored, else 1)
+    int* zidx = nullptr;        // [G][nz][nz][4] index of zeta per ordered pair
     double* zeta_dev = nullptr; // [G][nzeta_max]
     int nzeta_max = 0;
     std::vector<int> nzeta;     // per geometry
-    bool d_valid = false;
-    double* partial = nullptr;  // reduction partials
-    size_t partial_count = 0;
+    std::vector<double> zeta_host;
+    std::vector<int> zidx_host;
+    bool d_valid = false;       // D holds the current geometry (stored mode)
+    double* dW = nullptr;       // FP64 scratch for the derivative transform
+    void* dF = nullptr;
+    double* dscale = nullptr;   // -1/(Lx Ly) per zeta of a chunk
+    int dchunk = 0;
+    double* partial = nullptr;  // reduction partials [batch_max][nblk][2 nz]
+    int nblk = 0;
     // launch configuration chosen by the autotuner
     int tuned = 0;
 };
@@ -198,9 +205,12 @@ void free_plan_memory(hfd_plan p)
     if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->Qs, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
-                    p->D, p->zidx, p->zeta_dev, p->partial};
+                    p->D, p->zidx, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    p->dW = nullptr;
+    p->dF = nullptr;
+    p->dscale = nullptr;
     p->Q = p->Qs = p->lp = p->twx = p->twy = p->X1 = p->Mh = p->Hh = nullptr;
     p->twx64 = p->twy64 = nullptr;
     p->D = nullptr;
@@ -323,6 +333,144 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
     if (scale) (void)hipFree(scale);
     p->d_valid = false;
     return st;
+}
+
+
+// Distinct z offsets zeta = (interface of the target) - (interface of the
+// source) over all ordered layer pairs, merged when equal to 1e-12 relative.
+void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>& zidx,
+                        std::vector<int>& count, int& nmax)
+{
+    const int nz = p->nz, G = p->G;
+    std::vector<std::vector<double>> per(G);
+    zidx.assign((size_t)G * nz * nz * 4, 0);
+    count.assign(G, 0);
+    nmax = 0;
+    for (int g = 0; g < G; ++g) {
+        const double* t = &p->thick[(size_t)g * nz];
+        const double* z = &p->zbot[(size_t)g * nz];
+        std::vector<double> all;
+        auto zs = [&](int i, int j, int c) {
+            const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
+            switch (c) {
+            case 0: return ti - bj;
+            case 1: return bi - bj;
+            case 2: return ti - tj;
+            default: return bi - tj;
+            }
+        };
+        for (int i = 0; i < nz; ++i)
+            for (int j = 0; j < nz; ++j)
+                for (int c = 0; c < 4; ++c) all.push_back(zs(i, j, c));
+        std::vector<double> u = all;
+        std::sort(u.begin(), u.end());
+        std::vector<double> m;
+        for (double v : u) {
+            if (!m.empty() && std::fabs(v - m.back()) <= 1e-12 * std::max(1.0, std::fabs(v))) continue;
+            m.push_back(v);
+        }
+        // snap values within rounding of zero to exactly zero (touching interfaces)
+        double scale = 0.0;
+        for (int l = 0; l < nz; ++l) scale = std::max(scale, std::fabs(z[l]) + t[l]);
+        for (double& v : m)
+            if (std::fabs(v) <= 1e-12 * std::max(1.0, scale)) v = 0.0;
+        for (int i = 0; i < nz; ++i)
+            for (int j = 0; j < nz; ++j)
+                for (int c = 0; c < 4; ++c) {
+                    const double v = zs(i, j, c);
+                    int best = 0;
+                    double bd = 1e300;
+                    for (int k = 0; k < (int)m.size(); ++k)
+                        if (std::fabs(m[k] - v) < bd) { bd = std::fabs(m[k] - v); best = k; }
+                    zidx[(((size_t)g * nz + i) * nz + j) * 4 + c] = best;
+                }
+        per[g] = m;
+        count[g] = (int)m.size();
+        nmax = std::max(nmax, (int)m.size());
+    }
+    zeta.assign((size_t)G * nmax, 0.0);
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < count[g]; ++k) zeta[(size_t)g * nmax + k] = per[g][k];
+}
+
+// Allocate (or re-allocate) the derivative buffers and upload the offsets.
+hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
+{
+    std::vector<double> zeta;
+    std::vector<int> zidx, count;
+    int nmax = 0;
+    derivative_offsets(p, zeta, zidx, count, nmax);
+    const bool store = p->flags & HFD_STORE_DTENSOR;
+    const int dgeoms = store ? p->G : 1;
+    const long long per_geom = (long long)nmax * 6 * p->QX * p->QY;
+    if (nmax > p->nzeta_max || !p->D) {
+        if (p->D) (void)hipFree(p->D);
+        if (p->zeta_dev) (void)hipFree(p->zeta_dev);
+        p->D = nullptr;
+        p->zeta_dev = nullptr;
+        HFD_TRY(dev_alloc(&p->D, (size_t)per_geom * dgeoms * p->rsz, "derivative tensor"));
+        HFD_TRY(dev_alloc(&p->zeta_dev, sizeof(double) * zeta.size(), "derivative offsets"));
+        p->nzeta_max = nmax;
+        p->d_geom_stride = per_geom;
+        p->d_geoms = dgeoms;
+    }
+    if (!p->zidx) HFD_TRY(dev_alloc(&p->zidx, sizeof(int) * zidx.size(), "offset index"));
+    const long long plane = (long long)p->Lx * p->Ly;
+    const long long per_z = 6 * plane * 8;
+    const int chunk = (int)std::max(1LL, std::min<long long>(nmax, (256LL << 20) / per_z));
+    if (chunk > p->dchunk) {
+        if (p->dW) (void)hipFree(p->dW);
+        if (p->dF) (void)hipFree(p->dF);
+        if (p->dscale) (void)hipFree(p->dscale);
+        p->dW = nullptr;
+        p->dF = nullptr;
+        p->dscale = nullptr;
+        HFD_TRY(dev_alloc(&p->dW, (size_t)chunk * per_z, "derivative scratch"));
+        HFD_TRY(dev_alloc(&p->dF, (size_t)chunk * per_z, "derivative scratch"));
+        HFD_TRY(dev_alloc(&p->dscale, sizeof(double) * chunk, "derivative scale"));
+        std::vector<double> sc((size_t)chunk, -1.0 / (double)plane);
+        HFD_HIP(hipMemcpyAsync(p->dscale, sc.data(), sizeof(double) * chunk, hipMemcpyHostToDevice, s));
+        p->dchunk = chunk;
+    }
+    p->zeta_host = zeta;
+    p->zidx_host = zidx;
+    p->nzeta = count;
+    HFD_HIP(hipMemcpyAsync(p->zeta_dev, p->zeta_host.data(), sizeof(double) * zeta.size(),
+                           hipMemcpyHostToDevice, s));
+    HFD_HIP(hipMemcpyAsync(p->zidx, p->zidx_host.data(), sizeof(int) * zidx.size(),
+                           hipMemcpyHostToDevice, s));
+    // partial sums of the reduction
+    const int nblk = (int)(((long long)p->M * p->Ly + 255) / 256);
+    if (nblk != p->nblk || !p->partial) {
+        if (p->partial) (void)hipFree(p->partial);
+        p->partial = nullptr;
+        HFD_TRY(dev_alloc(&p->partial, sizeof(double) * (size_t)p->batch_max * nblk * 2 * p->nz,
+                          "reduction partials"));
+        p->nblk = nblk;
+    }
+    HFD_HIP(hipStreamSynchronize(s));
+    p->d_valid = false;
+    return HFD_OK;
+}
+
+// D(zeta) of geometry g into slot `slot` of p->D: FP64 lattice of the
+// lateral-stencilled z-derivative, FP64 2D FFT, packed to plan precision.
+hfd_status compute_derivatives(hfd_plan p, int g, int slot, hipStream_t s)
+{
+    const long long plane = (long long)p->Lx * p->Ly;
+    const int nzt = p->nzeta[g];
+    char* dst = (char*)p->D + (size_t)slot * p->d_geom_stride * p->rsz;
+    for (int z0 = 0; z0 < nzt; z0 += p->dchunk) {
+        const int nc = std::min(p->dchunk, nzt - z0);
+        HFD_HIP(hipMemsetAsync(p->dW, 0, (size_t)nc * 6 * plane * 8, s));
+        HFD_HIP(launch_dtensor_real(p->dW, p->zeta_dev + (size_t)g * p->nzeta_max + z0, nc, p->nx,
+                                    p->ny, p->Lx, p->Ly, p->dx, p->dy, s));
+        HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));
+        HFD_HIP(launch_yfwd(true, p->Ly, p->dF, p->dF, p->Ly, (long long)nc * 6 * p->M, p->twy64, s));
+        HFD_HIP(launch_pack(p->fp64, p->dF, dst + (size_t)z0 * 6 * p->QX * p->QY * p->rsz, p->dscale,
+                            nc, 6, p->M, p->Ly, p->QX, p->QY, s));
+    }
+    return HFD_OK;
 }
 
 hfd_status check_field_args(hfd_plan p, const void* a, const void* b, int batch, const char* na,
@@ -474,6 +622,14 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         st = upload_twiddles(p, s);
         if (st) break;
         st = build_tensor(p, s);
+        if (st) break;
+        st = setup_derivatives(p, s);
+        if (st) break;
+        if (flags & HFD_STORE_DTENSOR) {
+            for (int g = 0; g < n_geom && st == HFD_OK; ++g) st = compute_derivatives(p, g, g, s);
+            if (st == HFD_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(HFD_EHIP, "sync failed");
+            p->d_valid = (st == HFD_OK);
+        }
     } while (0);
     if (st) {
         free_plan_memory(p);
@@ -497,7 +653,15 @@ hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* 
     HFD_HIP(dg.set(p->dev));
     p->thick = t;
     p->zbot = z;
-    return build_tensor(p, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    HFD_TRY(build_tensor(p, s));
+    HFD_TRY(setup_derivatives(p, s));
+    if (p->flags & HFD_STORE_DTENSOR) {
+        for (int g = 0; g < p->G; ++g) HFD_TRY(compute_derivatives(p, g, g, s));
+        HFD_HIP(hipStreamSynchronize(s));
+        p->d_valid = true;
+    }
+    return HFD_OK;
 }
 
 hfd_status hfd_demag_field(hfd_plan p, const void* m, void* h, int batch, void* stream)
@@ -518,11 +682,36 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     if (grad_thickness) {
         HFD_TRY(check_field_args(p, m, grad_h, batch, "m", "grad_h"));
         if ((uintptr_t)grad_thickness & 7) return fail(HFD_EINVAL, "grad_thickness must be 8-byte aligned");
-        return fail(HFD_ENOTSUP, "thickness gradient not available in this build");
     }
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
-    return run_field(p, grad_h, grad_m, batch, 1, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    // (dh/dm)^T grad_h = T (dh/dm) T^-1 grad_h
+    if (grad_m) HFD_TRY(run_field(p, grad_h, grad_m, batch, 1, s));
+    if (!grad_thickness) return HFD_OK;
+    const int nsig = batch * 3 * p->nz;
+    const long long ncols = (long long)nsig * p->M;
+    const long long sig_stride = (long long)p->ny * p->nx;
+    HFD_HIP(launch_xfwd(p->fp64, p->Lx, m, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
+    HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
+    HFD_HIP(launch_xfwd(p->fp64, p->Lx, grad_h, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
+    HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Hh, p->ny, ncols, p->twy, s));
+    const int bpg = batch / p->G;
+    if (p->d_valid) {
+        HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
+                             p->D, p->d_geom_stride, p->zidx, 0, p->lp, bpg, p->QX, p->QY, p->partial,
+                             p->nblk, s));
+    } else {
+        // recompute the derivative tensor of one stack at a time
+        for (int g = 0; g < p->G; ++g) {
+            HFD_TRY(compute_derivatives(p, g, 0, s));
+            HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g * bpg, bpg, p->Q,
+                                 p->q_geom_stride, p->D, p->d_geom_stride, p->zidx, g, p->lp, bpg,
+                                 p->QX, p->QY, p->partial, p->nblk, s));
+        }
+    }
+    HFD_HIP(launch_tgrad_finish(p->partial, p->nblk, batch, p->nz, grad_thickness, s));
+    return HFD_OK;
 }
 
 hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int reps, void* stream,

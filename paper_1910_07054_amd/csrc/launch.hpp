@@ -42,13 +42,13 @@ hipError_t launch_split_tensor(const float* Q, void* Qs, int G, int nz, int QX, 
                                const float* lp, int Lxy_unused, hipStream_t s);
 long long split_tensor_bytes(int G, int nz, int QX, int QY);
 
-// thickness-gradient reduction over the spectra
-hipError_t launch_tgrad_reduce(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY,
-                               int B, const void* Q, long long q_geom_stride, const float* D,
-                               long long d_geom_stride, const int* zidx, const void* lp, int bpg,
-                               int QX, int QY, double* partial, int nblk_x, hipStream_t s);
-hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const void* lp,
-                               bool fp64, int bpg, double* grad_t, hipStream_t s);
+// thickness-gradient reduction over the spectra (states b0 .. b0+nb-1)
+hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
+                        int nb, const void* Q, long long qgs, const void* D, long long dgs,
+                        const int* zidx, int g_first, const void* lp, int bpg, int QX, int QY,
+                        double* partial, int nblk, hipStream_t s);
+hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, double* grad_t,
+                               hipStream_t s);
 
 // tensor setup (FP64)
 struct PairGeoH {

@@ -9,7 +9,9 @@ static hipError_t xfwd_t(const void* in, void* out, int nx, int ny, long long is
                          const void* tw, hipStream_t s)
 {
     using S = XPassShape<R, LX>;
-    if (S::LDS > 65536) {
+    static bool attr_done = false;
+    if (S::LDS > 65536 && !attr_done) {
+        attr_done = true;
         hipError_t e = hipFuncSetAttribute((const void*)k_xfwd<R, LX>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS);
         if (e != hipSuccess) return e;
@@ -25,7 +27,9 @@ static hipError_t xinv_t(const void* in, void* out, int nx, int ny, long long os
                          const void* tw, hipStream_t s)
 {
     using S = XPassShape<R, LX>;
-    if (S::LDS > 65536) {
+    static bool attr_done = false;
+    if (S::LDS > 65536 && !attr_done) {
+        attr_done = true;
         hipError_t e = hipFuncSetAttribute((const void*)k_xinv<R, LX>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS);
         if (e != hipSuccess) return e;
