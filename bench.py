@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--split", action="store_true", help="force the five-pass path")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -121,6 +123,14 @@ def main():
     h = torch.empty_like(m)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     with torch.cuda.stream(stream):
         for _ in range(max(args.warmup, 1)):

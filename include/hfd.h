@@ -153,7 +153,8 @@ typedef struct {
 hfd_status hfd_get_info(hfd_plan plan, hfd_info *info);
 
 /* Copy the stored Fourier tensor of stack `geom` to the HOST buffer `dst`:
- * layout [P_u][5][Lx/2+1][Ly/2+1] in the plan's precision, P_u = nz(nz+1)/2
+ * layout [Lx/2+1][P_u][5][Ly/2+1] (kx, pair, component, ky) in the plan's
+ * precision, P_u = nz(nz+1)/2
  * unique pairs i <= j in row-major upper-triangle order, components
  * (xx, yy, xy, xz, yz) of t_i * (-DFT2(N^{ij}) / (Lx Ly)); real parts for
  * xx, yy, xy, imaginary parts for xz, yz (the only non-zero parts by

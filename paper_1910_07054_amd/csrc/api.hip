@@ -297,8 +297,9 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
                 if (e == hipSuccess)
                     e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
                 if (e == hipSuccess) {
-                    char* qdst = (char*)p->Q + ((size_t)g * p->q_geom_stride + (size_t)u0 * 5 * p->QX * p->QY) * p->rsz;
-                    e = launch_pack(p->fp64, F, qdst, scale + u0, np, 5, p->M, p->Ly, p->QX, p->QY, s);
+                    char* qdst = (char*)p->Q + (size_t)g * p->q_geom_stride * p->rsz;
+                    e = launch_pack(p->fp64, F, qdst, scale + u0, np, 5, p->M, p->Ly, p->QX, p->QY,
+                                    u0, p->P, s);
                 }
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -468,7 +469,7 @@ hfd_status compute_derivatives(hfd_plan p, int g, int slot, hipStream_t s)
         HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));
         HFD_HIP(launch_yfwd(true, p->Ly, p->dF, p->dF, p->Ly, (long long)nc * 6 * p->M, p->twy64, s));
         HFD_HIP(launch_pack(p->fp64, p->dF, dst + (size_t)z0 * 6 * p->QX * p->QY * p->rsz, p->dscale,
-                            nc, 6, p->M, p->Ly, p->QX, p->QY, s));
+                            nc, 6, p->M, p->Ly, p->QX, p->QY, 0, 0, s));
     }
     return HFD_OK;
 }

@@ -9,8 +9,10 @@
 //                                   the two real columns kx = 0 and kx = Lx/2
 //                                   as X(0) + i X(Lx/2)
 //   Mh, Hh [B][S][M][Ly]            full y spectra (five-pass path only)
-//   Q      [G][P][5][Lx/2+1][Ly/2+1] Fourier tensor, unique pairs i <= j,
-//                                   components xx, yy, xy, xz, yz of
+//   Q      [G][Lx/2+1][P][5][Ly/2+1] Fourier tensor on the quadrant kx in
+//                                   [0, Lx/2], ky in [0, Ly/2] (contiguous per
+//                                   kx column), unique pairs i <= j, components
+//                                   xx, yy, xy, xz, yz of
 //                                   t_i * (-DFT2(N^{ij}) / (Lx Ly)); real part
 //                                   for xx, yy, xy, imaginary part for xz, yz
 //   lp     [G][2][nz]               1 / t_l and -t_l / (Lx Ly) (trace of the
@@ -185,76 +187,64 @@ __device__ __forceinline__ void block_apply(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, 
     hz.y += xz * X.x + yz * Y.x + zz * Z.y;
 }
 
-template <typename R, int NZMAX, bool SAME, class InA, class InB>
-__device__ __forceinline__ void mix2(int nz, InA ina, InB inb, cpx<R>* Ha, cpx<R>* Hb,
-                                     const R* __restrict__ qa, const R* __restrict__ qb,
-                                     long long cs, R sb, const R* dg)
+// One frequency point: H_i += S^{ij} M_j and, for i < j, H_j += conj(S^{ij}) M_i.
+// q points at pair 0, component 0 of the point's tensor column (pair stride
+// 5 * QY, component stride QY); sg is the sign of the ky-odd components.
+template <typename R, int NZMAX, class In>
+__device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const R* __restrict__ q, int QY,
+                                     R sg, const R* dg)
 {
 #pragma unroll
-    for (int k = 0; k < 3 * NZMAX; ++k) {
-        Ha[k] = {R(0), R(0)};
-        Hb[k] = {R(0), R(0)};
-    }
+    for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {R(0), R(0)};
     int u = 0;
 #pragma unroll
     for (int i = 0; i < NZMAX; ++i) {
         if (i < nz) {
-        const cpx<R> aix = ina(0, i), aiy = ina(1, i), aiz = ina(2, i);
-        const cpx<R> bix = inb(0, i), biy = inb(1, i), biz = inb(2, i);
+            // tensor row i (pairs (i, j >= i)) loaded before use
+            R qv[NZMAX][5];
 #pragma unroll
-        for (int j = i; j < NZMAX; ++j) {
-            if (j < nz) {
-            const long long o = (long long)u * 5 * cs;
-            const R axx = qa[o], ayy = qa[o + cs], axy = qa[o + 2 * cs], axz = qa[o + 3 * cs],
-                    ayz = qa[o + 4 * cs];
-            R bxx, byy, bxy, bxz, byz;
-            if constexpr (SAME) {
-                bxx = axx; byy = ayy; bxy = axy; bxz = axz; byz = ayz;
-            } else {
-                bxx = qb[o]; byy = qb[o + cs]; bxy = qb[o + 2 * cs]; bxz = qb[o + 3 * cs];
-                byz = qb[o + 4 * cs];
+            for (int j = i; j < NZMAX; ++j)
+                if (j < nz) {
+                    const R* qq = q + (long long)(u + j - i) * 5 * QY;
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) qv[j][c] = qq[c * QY];
+                }
+            const cpx<R> ix = in(0, i), iy = in(1, i), iz = in(2, i);
+#pragma unroll
+            for (int j = i; j < NZMAX; ++j) {
+                if (j < nz) {
+                    const R xx = qv[j][0], yy = qv[j][1], xy = sg * qv[j][2], xz = qv[j][3],
+                            yz = sg * qv[j][4];
+                    R zz = -(xx + yy);
+                    if (i == j) zz += dg[i];
+                    if (i == j) {
+                        block_apply(H[i], H[NZMAX + i], H[2 * NZMAX + i], ix, iy, iz, xx, yy, zz, xy,
+                                    xz, yz);
+                    } else {
+                        const cpx<R> jx = in(0, j), jy = in(1, j), jz = in(2, j);
+                        block_apply(H[i], H[NZMAX + i], H[2 * NZMAX + i], jx, jy, jz, xx, yy, zz, xy,
+                                    xz, yz);
+                        block_apply(H[j], H[NZMAX + j], H[2 * NZMAX + j], ix, iy, iz, xx, yy, zz, xy,
+                                    -xz, -yz);
+                    }
+                }
             }
-            R azz = -(axx + ayy), bzz = -(bxx + byy);
-            if (i == j) {
-                azz += dg[i];
-                bzz += dg[i];
-            }
-            bxy *= sb;
-            byz *= sb;
-            if (i == j) {
-                block_apply(Ha[i], Ha[NZMAX + i], Ha[2 * NZMAX + i], aix, aiy, aiz, axx, ayy, azz,
-                            axy, axz, ayz);
-                block_apply(Hb[i], Hb[NZMAX + i], Hb[2 * NZMAX + i], bix, biy, biz, bxx, byy, bzz,
-                            bxy, bxz, byz);
-            } else {
-                const cpx<R> ajx = ina(0, j), ajy = ina(1, j), ajz = ina(2, j);
-                const cpx<R> bjx = inb(0, j), bjy = inb(1, j), bjz = inb(2, j);
-                block_apply(Ha[i], Ha[NZMAX + i], Ha[2 * NZMAX + i], ajx, ajy, ajz, axx, ayy, azz,
-                            axy, axz, ayz);
-                block_apply(Hb[i], Hb[NZMAX + i], Hb[2 * NZMAX + i], bjx, bjy, bjz, bxx, byy, bzz,
-                            bxy, bxz, byz);
-                block_apply(Ha[j], Ha[NZMAX + j], Ha[2 * NZMAX + j], aix, aiy, aiz, axx, ayy, azz,
-                            axy, -axz, -ayz);
-                block_apply(Hb[j], Hb[NZMAX + j], Hb[2 * NZMAX + j], bix, biy, biz, bxx, byy, bzz,
-                            bxy, -bxz, -byz);
-            }
-            ++u;
-            }
-        }
+            u += nz - i;
         }
     }
 }
 
 template <int LY>
 struct FusedShape {
-    static constexpr int NT = LY / 2 < 64 ? 64 : LY / 2;
+    static constexpr int NT = LY < 64 ? 64 : LY;
 };
 
 // ---------------------------------------------------------------------------
 // Fused y pass for one kx column of one state: forward y-DFT of the 3 nz
 // signals (input zero padded from ny to LY), z-mixing per ky, inverse y-DFT
-// cropped to ny.  All 3 nz spectra stay in LDS.  Thread t mixes the ky pair
-// (t, LY - t) (t = 0: ky = 0 and LY/2), which share one quadrant tensor entry.
+// cropped to ny.  All 3 nz spectra stay in LDS.  Lanes 2t and 2t+1 mix the ky
+// pair (t, LY - t) (t = 0: ky = 0 and LY/2), which share one quadrant tensor
+// entry, so the two lanes read the same addresses.
 // Column 0 carries kx = 0 and kx = Lx/2 packed as A + iB; they are separated
 // with the Hermitian symmetry in ky, mixed with their own tensor rows and
 // packed again.  adjoint != 0 applies the transpose (inputs scaled by 1/t
@@ -286,7 +276,7 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     }
     __syncthreads();
 
-    const int t = tid;
+    const int t = tid >> 1, p = tid & 1;
     if (t < LY / 2) {
         const R* lpg = lp + (long long)geom * 2 * nz;
         R invt[NZMAX], dg[NZMAX];
@@ -295,70 +285,58 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             invt[i] = i < nz ? lpg[i] : R(0);
             dg[i] = i < nz ? lpg[nz + i] : R(0);
         }
+        const int P = nz * (nz + 1) / 2;
+        const long long colstride = (long long)P * 5 * QY;   // one kx column of the tensor
         const R* Qg = Q + (long long)geom * q_geom_stride;
-        const long long cs = (long long)QX * QY;
-        const int ky1 = t, ky2 = (t == 0) ? LY / 2 : LY - t;
         const R one = R(1);
-        // input scale: 1/t_l on the sources for the transpose, 1 otherwise
         auto isc = [&](int l) -> R { return adjoint ? invt[l] : one; };
         auto osc = [&](int l) -> R { return adjoint ? one : invt[l]; };
-        cpx<R> Ha[3 * NZMAX], Hb[3 * NZMAX];
-        auto store = [&](const cpx<R>* A, int ky) {
+        cpx<R> H[3 * NZMAX];
+        auto store = [&](int ky) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int l = 0; l < NZMAX; ++l)
-                    if (l < nz) sh[(c * nz + l) * LY + ky] = cscale(A[c * NZMAX + l], osc(l));
+                    if (l < nz) sh[(c * nz + l) * LY + ky] = cscale(H[c * NZMAX + l], osc(l));
         };
+        const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);   // this lane's point
+        const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);        // its quadrant column
+        const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
         if (kx != 0) {
-            auto ina = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky1], isc(l)); };
-            auto inb = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky2], isc(l)); };
-            const R* qrow = Qg + (long long)kx * QY;
-            if (t != 0) mix2<R, NZMAX, true>(nz, ina, inb, Ha, Hb, qrow + t, qrow + t, cs, R(-1), dg);
-            else mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, qrow, qrow + LY / 2, cs, R(1), dg);
-            store(Ha, ky1);
-            store(Hb, ky2);
-        } else {
+            auto in = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky], isc(l)); };
+            mix1<R, NZMAX>(nz, in, H, Qg + kx * colstride + kq, QY, sg, dg);
+            store(ky);
+        } else if (t != 0) {
             // column 0 holds Z = A + iB with A the kx = 0 and B the kx = Lx/2
-            // column: A(ky) = (Z(ky) + conj Z(-ky))/2, B(ky) = (Z(ky) - conj Z(-ky))/(2i)
-            const R* row0 = Qg;
-            const R* rowM = Qg + (long long)M * QY;
-            if (t != 0) {
-                auto ina = [&](int c, int l) -> cpx<R> {
-                    const cpx<R> z1 = sh[(c * nz + l) * LY + ky1], z2 = sh[(c * nz + l) * LY + ky2];
-                    return cscale(cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}, isc(l));
-                };
-                auto inb = [&](int c, int l) -> cpx<R> {
-                    const cpx<R> z1 = sh[(c * nz + l) * LY + ky1], z2 = sh[(c * nz + l) * LY + ky2];
-                    return cscale(cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)}, isc(l));
-                };
-                mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, row0 + t, rowM + t, cs, R(1), dg);
-                // W(ky) = HA + i HB ; W(-ky) = conj(HA) + i conj(HB)
+            // column: A(ky) = (Z(ky) + conj Z(-ky))/2, B(ky) = (Z(ky) - conj Z(-ky))/(2i).
+            // Lane p = 0 mixes A(t) with row 0, lane p = 1 mixes B(t) with row M;
+            // W(t) = HA + i HB, W(-t) = conj(HA) + i conj(HB).
+            const int k1 = t, k2 = LY - t;
+            auto in = [&](int c, int l) -> cpx<R> {
+                const cpx<R> z1 = sh[(c * nz + l) * LY + k1], z2 = sh[(c * nz + l) * LY + k2];
+                const cpx<R> v = p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
+                                        : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
+                return cscale(v, isc(l));
+            };
+            mix1<R, NZMAX>(nz, in, H, Qg + (p == 0 ? 0 : (long long)M * colstride) + t, QY, R(1), dg);
 #pragma unroll
-                for (int k = 0; k < 3 * NZMAX; ++k) {
-                    const cpx<R> a = Ha[k], bb = Hb[k];
-                    Ha[k] = {a.x - bb.y, a.y + bb.x};
-                    Hb[k] = {a.x + bb.y, bb.x - a.y};
-                }
-                store(Ha, ky1);
-                store(Hb, ky2);
-            } else {
-                // ky = 0 and ky = LY/2 are their own mirror: A = Re Z, B = Im Z
-#pragma unroll
-                for (int pass = 0; pass < 2; ++pass) {
-                    const int kyp = pass == 0 ? 0 : LY / 2;
-                    auto ina = [&](int c, int l) -> cpx<R> {
-                        return {sh[(c * nz + l) * LY + kyp].x * isc(l), R(0)};
-                    };
-                    auto inb = [&](int c, int l) -> cpx<R> {
-                        return {sh[(c * nz + l) * LY + kyp].y * isc(l), R(0)};
-                    };
-                    mix2<R, NZMAX, false>(nz, ina, inb, Ha, Hb, row0 + kyp, rowM + kyp, cs, R(1), dg);
-#pragma unroll
-                    for (int k = 0; k < 3 * NZMAX; ++k) Ha[k] = {Ha[k].x - Hb[k].y, Ha[k].y + Hb[k].x};
-                    store(Ha, kyp);
-                }
+            for (int k = 0; k < 3 * NZMAX; ++k) {
+                const cpx<R> o = {__shfl_xor(H[k].x, 1), __shfl_xor(H[k].y, 1)};
+                const cpx<R> A = p == 0 ? H[k] : o, Bv = p == 0 ? o : H[k];
+                H[k] = p == 0 ? cpx<R>{A.x - Bv.y, A.y + Bv.x} : cpx<R>{A.x + Bv.y, Bv.x - A.y};
             }
+            store(p == 0 ? k1 : k2);
+        } else {
+            // ky = 0 (p = 0) or LY/2 (p = 1), each its own mirror: A = Re Z, B = Im Z
+            const int kp = p == 0 ? 0 : LY / 2;
+            cpx<R> HA[3 * NZMAX];
+            auto inA = [&](int c, int l) -> cpx<R> { return {sh[(c * nz + l) * LY + kp].x * isc(l), R(0)}; };
+            auto inB = [&](int c, int l) -> cpx<R> { return {sh[(c * nz + l) * LY + kp].y * isc(l), R(0)}; };
+            mix1<R, NZMAX>(nz, inA, HA, Qg + kp, QY, R(1), dg);
+            mix1<R, NZMAX>(nz, inB, H, Qg + (long long)M * colstride + kp, QY, R(1), dg);
+#pragma unroll
+            for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {HA[k].x - H[k].y, HA[k].y + H[k].x};
+            store(kp);
         }
     }
     __syncthreads();
@@ -445,7 +423,8 @@ __global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ 
     cpx<R>* hb = Hh + ((long long)b * S * M + kx) * LY;
     const R* lpg = lp + (long long)geom * 2 * nz;
     const R* Qg = Q + (long long)geom * q_geom_stride;
-    const long long cs = (long long)QX * QY;
+    const long long cs = QY;                          // component stride
+    const long long colstride = (long long)nz * (nz + 1) / 2 * 5 * QY;
     const int half = LY / 2;
     const int kq = ky <= half ? ky : LY - ky;        // quadrant column
     const R sg = ky <= half ? R(1) : R(-1);          // sign of the ky-odd components
@@ -463,7 +442,7 @@ __global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ 
             const int npts = (kx == 0) ? 2 : 1;
             for (int p = 0; p < npts; ++p) {
                 const int row = (kx == 0) ? (p == 0 ? 0 : M) : kx;
-                const R* q = Qg + (long long)u * 5 * cs + (long long)row * QY + kq;
+                const R* q = Qg + (long long)row * colstride + (long long)u * 5 * QY + kq;
                 const R xx = q[0], yy = q[cs], xy = q[2 * cs] * sg, xz = q[3 * cs] * simag,
                         yz = q[4 * cs] * sg * simag;
                 const R zz = -(xx + yy) + dgi;

@@ -58,7 +58,10 @@ hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx,
                               int Ly, double dx, double dy, int mode, hipStream_t s);
 hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
                                int Ly, double dx, double dy, hipStream_t s);
+// comps 5: field tensor, written at pairs pair0.. of a [QX][pair_total][5][QY] array;
+// comps 6: derivative tables, [npairs][6][QX][QY]
 hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
-                       int comps, int M, int Ly, int QX, int QY, hipStream_t s);
+                       int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
+                       hipStream_t s);
 
 }  // namespace hfd

@@ -384,7 +384,8 @@ __global__ __launch_bounds__(128) void k_dtensor_real(double* __restrict__ W,
 template <typename R>
 __global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F, R* __restrict__ Qout,
                                               const double* __restrict__ scale, int npairs, int comps,
-                                              int M, int Ly, int QX, int QY)
+                                              int M, int Ly, int QX, int QY, int pair0,
+                                              int pair_total)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)comps * QX * QY;
@@ -404,7 +405,12 @@ __global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F,
         val = Fs[(long long)kx * Ly + ky];
     }
     const bool imag = (c6 == 4 || c6 == 5);
-    Qout[idx] = (R)((imag ? val.y : val.x) * scale[u]);
+    // comps == 5 (field tensor): [kx][pair][comp][ky] with pair_total pairs per
+    // column; comps == 6 (derivative tables): [pair][comp][kx][ky]
+    const long long o = comps == 5
+        ? (((long long)kx * pair_total + pair0 + u) * 5 + c) * QY + ky
+        : idx;
+    Qout[o] = (R)((imag ? val.y : val.x) * scale[u]);
 }
 
 }  // namespace hfd

@@ -148,11 +148,11 @@ __global__ __launch_bounds__(256) void k_tgrad(const cpx<R>* __restrict__ Mh,
                         if (pass == 0) {
                             const int a = i < j ? i : j, bq = i < j ? j : i;
                             const int u = a * nz - a * (a - 1) / 2 + (bq - a);
-                            const R* q = Qg + (long long)u * 5 * cs + (long long)row * QY + kq;
+                            const R* q = Qg + ((long long)row * (nz * (nz + 1) / 2) + u) * 5 * QY + kq;
                             const double simag = i <= j ? 1.0 : -1.0;
-                            const double xx = q[0], yy = q[cs], xy = sgy * (double)q[2 * cs];
-                            const double xz = simag * (double)q[3 * cs];
-                            const double yz = simag * sgy * (double)q[4 * cs];
+                            const double xx = q[0], yy = q[QY], xy = sgy * (double)q[2 * QY];
+                            const double xz = simag * (double)q[3 * QY];
+                            const double yz = simag * sgy * (double)q[4 * QY];
                             const double zz = -(xx + yy) + (i == j ? (double)lpg[nz + i] : 0.0);
                             // stored blocks are t_i T^{ij}
                             PT = contract<R>(X, xx, yy, zz, xy, xz, yz) / ti;

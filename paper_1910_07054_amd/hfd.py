@@ -202,7 +202,7 @@ class Plan:
         inf = self.info()
         P = self.nz * (self.nz + 1) // 2
         QX, QY = inf.Lx // 2 + 1, inf.Ly // 2 + 1
-        out = np.empty((P, 5, QX, QY), dtype=np.float64 if self.fp64 else np.float32)
+        out = np.empty((QX, P, 5, QY), dtype=np.float64 if self.fp64 else np.float32)
         _check(load().hfd_export_fourier_tensor(self.handle, int(geom), out.ctypes.data, out.nbytes))
         return out
 

@@ -38,7 +38,7 @@ def run_field(plan, m_np, stream=None):
 
 def expected_quadrant(Ntil: np.ndarray, thick: np.ndarray, Lx: int, Ly: int) -> np.ndarray:
     """Stored-tensor convention from the oracle's DFT of the pair tables:
-    [P][5][Lx/2+1][Ly/2+1] with (xx, yy, xy) real and (xz, yz) imaginary parts
+    [Lx/2+1][P][5][Ly/2+1] with (xx, yy, xy) real and (xz, yz) imaginary parts
     of t_i * (-Ntil / (Lx Ly)), unique pairs i <= j."""
     nz = Ntil.shape[0]
     QX, QY = Lx // 2 + 1, Ly // 2 + 1
@@ -48,4 +48,4 @@ def expected_quadrant(Ntil: np.ndarray, thick: np.ndarray, Lx: int, Ly: int) -> 
             T = thick[i] * (-Ntil[i, j] / (Lx * Ly))          # [6][Ly][Lx]
             q = T[:, :QY, :QX].transpose(0, 2, 1)               # [6][QX][QY]
             out.append(np.stack([q[0].real, q[1].real, q[3].real, q[4].imag, q[5].imag]))
-    return np.array(out)
+    return np.array(out).transpose(2, 0, 1, 3)

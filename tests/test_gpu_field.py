@@ -54,7 +54,7 @@ def test_fourier_tensor_matches_oracle(fp64):
     for i in range(3):
         for j in range(i, 3):
             Tzz = (t[i] * (-Nt[i, j, 2] / (inf.Lx * inf.Ly))).real[: inf.Ly // 2 + 1, : inf.Lx // 2 + 1].T
-            zz = -(got[u, 0] + got[u, 1]) + (-t[i] / (inf.Lx * inf.Ly) if i == j else 0.0)
+            zz = -(got[:, u, 0] + got[:, u, 1]) + (-t[i] / (inf.Lx * inf.Ly) if i == j else 0.0)
             assert np.abs(zz - Tzz).max() < tol * scale * 4
             u += 1
     plan.destroy()
