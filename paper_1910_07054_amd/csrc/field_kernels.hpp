@@ -27,7 +27,8 @@ struct XPassShape {
     static constexpr int M = LX / 2;
     static constexpr int V = fft_vals(M);
     static constexpr int GT = M / V;
-    static constexpr int NT = 256;
+    // 16 groups (one row each) per block where the block size allows
+    static constexpr int NT = GT * 16 < 256 ? 256 : (GT * 16 > 1024 ? 1024 : GT * 16);
     static constexpr int NG = NT / GT;
     static constexpr int RS = M + 1;               // padded LDS row stride
     // rows per block: at least 16 (or one per group), halved until the tile
@@ -49,7 +50,7 @@ struct XPassShape {
 // z[n] = x[2n] + i x[2n+1] followed by the even/odd split.
 // ---------------------------------------------------------------------------
 template <typename R, int LX>
-__global__ __launch_bounds__(256) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
+__global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
                                               int nx, int ny, long long in_sig_stride,
                                               int in_row_stride, const cpx<R>* __restrict__ twx)
 {
@@ -61,19 +62,31 @@ __global__ __launch_bounds__(256) void k_xfwd(const R* __restrict__ in, cpx<R>* 
     const int y0 = blockIdx.x * TY;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
     const R* base = in + (long long)sig * in_sig_stride;
+    Twiddles<R, M> tw;
+    tw.load(g, twx, 2);
 
     for (int r = grp; r < TY; r += NG) {
         const int y = y0 + r;
         if (y >= ny) break;
         cpx<R>* row = sh + r * RS;
         const R* src = base + (long long)y * in_row_stride;
-        wave_fft<R, M, false>(
-            row, g, twx, 2,
-            [&](int pos) -> cpx<R> {
-                const int n0 = 2 * pos;
-                return {n0 < nx ? src[n0] : R(0), n0 + 1 < nx ? src[n0 + 1] : R(0)};
-            },
-            [&](int pos, cpx<R> v) { row[pos] = v; });
+        if ((nx & 1) == 0 && (in_row_stride & 1) == 0) {
+            // even rows: (x[2n], x[2n+1]) is one aligned 2-element load
+            const cpx<R>* src2 = reinterpret_cast<const cpx<R>*>(src);
+            const int nh = nx >> 1;
+            wave_fft<R, M, false>(
+                row, g, tw,
+                [&](int pos) -> cpx<R> { return pos < nh ? src2[pos] : cpx<R>{R(0), R(0)}; },
+                [&](int pos, cpx<R> v) { row[pos] = v; });
+        } else {
+            wave_fft<R, M, false>(
+                row, g, tw,
+                [&](int pos) -> cpx<R> {
+                    const int n0 = 2 * pos;
+                    return {n0 < nx ? src[n0] : R(0), n0 + 1 < nx ? src[n0 + 1] : R(0)};
+                },
+                [&](int pos, cpx<R> v) { row[pos] = v; });
+        }
     }
     __syncthreads();
     constexpr int HM = M / 2 + 1;
@@ -109,7 +122,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const R* __restrict__ in, cpx<R>* 
 // Unnormalized; the 1/(Lx Ly) is folded into the tensor.
 // ---------------------------------------------------------------------------
 template <typename R, int LX>
-__global__ __launch_bounds__(256) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
+__global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
                                               int nx, int ny, long long out_sig_stride,
                                               int out_row_stride, const cpx<R>* __restrict__ twx)
 {
@@ -121,6 +134,8 @@ __global__ __launch_bounds__(256) void k_xinv(const cpx<R>* __restrict__ in, R* 
     const int y0 = blockIdx.x * TY;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
     const cpx<R>* src = in + (long long)sig * M * ny;
+    Twiddles<R, M> tw;
+    tw.load(g, twx, 2);
     for (int idx = tid; idx < M * TY; idx += NT) {
         const int r = idx % TY, kx = idx / TY;
         const int y = y0 + r;
@@ -154,13 +169,23 @@ __global__ __launch_bounds__(256) void k_xinv(const cpx<R>* __restrict__ in, R* 
         if (y >= ny) break;
         cpx<R>* row = sh + r * RS;
         R* dst = obase + (long long)y * out_row_stride;
-        wave_fft<R, M, true>(
-            row, g, twx, 2, [&](int pos) -> cpx<R> { return row[pos]; },
-            [&](int pos, cpx<R> v) {
-                const int n0 = 2 * pos;
-                if (n0 < nx) dst[n0] = v.x;
-                if (n0 + 1 < nx) dst[n0 + 1] = v.y;
-            });
+        if ((nx & 1) == 0 && (out_row_stride & 1) == 0) {
+            cpx<R>* dst2 = reinterpret_cast<cpx<R>*>(dst);
+            const int nh = nx >> 1;
+            wave_fft<R, M, true>(
+                row, g, tw, [&](int pos) -> cpx<R> { return row[pos]; },
+                [&](int pos, cpx<R> v) {
+                    if (pos < nh) dst2[pos] = v;
+                });
+        } else {
+            wave_fft<R, M, true>(
+                row, g, tw, [&](int pos) -> cpx<R> { return row[pos]; },
+                [&](int pos, cpx<R> v) {
+                    const int n0 = 2 * pos;
+                    if (n0 < nx) dst[n0] = v.x;
+                    if (n0 + 1 < nx) dst[n0 + 1] = v.y;
+                });
+        }
     }
 }
 
@@ -179,20 +204,22 @@ template <typename R>
 __device__ __forceinline__ void block_apply(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, cpx<R> X, cpx<R> Y,
                                             cpx<R> Z, R xx, R yy, R zz, R xy, R xz, R yz)
 {
-    hx.x += xx * X.x + xy * Y.x - xz * Z.y;
-    hx.y += xx * X.y + xy * Y.y + xz * Z.x;
-    hy.x += xy * X.x + yy * Y.x - yz * Z.y;
-    hy.y += xy * X.y + yy * Y.y + yz * Z.x;
-    hz.x += -xz * X.y - yz * Y.y + zz * Z.x;
-    hz.y += xz * X.x + yz * Y.x + zz * Z.y;
+    // real parts (xx, yy, zz, xy) multiply, imaginary parts (i xz, i yz) rotate
+    hx.x = fma(xx, X.x, hx.x); hx.x = fma(xy, Y.x, hx.x); hx.x = fma(-xz, Z.y, hx.x);
+    hx.y = fma(xx, X.y, hx.y); hx.y = fma(xy, Y.y, hx.y); hx.y = fma(xz, Z.x, hx.y);
+    hy.x = fma(xy, X.x, hy.x); hy.x = fma(yy, Y.x, hy.x); hy.x = fma(-yz, Z.y, hy.x);
+    hy.y = fma(xy, X.y, hy.y); hy.y = fma(yy, Y.y, hy.y); hy.y = fma(yz, Z.x, hy.y);
+    hz.x = fma(-xz, X.y, hz.x); hz.x = fma(-yz, Y.y, hz.x); hz.x = fma(zz, Z.x, hz.x);
+    hz.y = fma(xz, X.x, hz.y); hz.y = fma(yz, Y.x, hz.y); hz.y = fma(zz, Z.y, hz.y);
 }
 
 // One frequency point: H_i += S^{ij} M_j and, for i < j, H_j += conj(S^{ij}) M_i.
-// q points at pair 0, component 0 of the point's tensor column (pair stride
-// 5 * QY, component stride QY); sg is the sign of the ky-odd components.
+// qcol views the tensor from a wave-uniform base; kq is the lane's element
+// offset of its (kx row, quadrant ky); pair u, component c sits at
+// (u * 5 + c) * QY + kq.  sg is the sign of the ky-odd components (xy, yz).
 template <typename R, int NZMAX, class In>
-__device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const R* __restrict__ q, int QY,
-                                     R sg, const R* dg)
+__device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
+                                     unsigned kq, int QY, R sg, const R* dg)
 {
 #pragma unroll
     for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {R(0), R(0)};
@@ -205,9 +232,9 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const R* __restri
 #pragma unroll
             for (int j = i; j < NZMAX; ++j)
                 if (j < nz) {
-                    const R* qq = q + (long long)(u + j - i) * 5 * QY;
 #pragma unroll
-                    for (int c = 0; c < 5; ++c) qv[j][c] = qq[c * QY];
+                    for (int c = 0; c < 5; ++c)
+                        qv[j][c] = qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY));
                 }
             const cpx<R> ix = in(0, i), iy = in(1, i), iz = in(2, i);
 #pragma unroll
@@ -250,10 +277,10 @@ struct FusedShape {
 // packed again.  adjoint != 0 applies the transpose (inputs scaled by 1/t
 // instead of the outputs).
 // ---------------------------------------------------------------------------
-template <typename R, int LY, int NZMAX>
+template <typename R, int LY, int NZMAX, bool ADJ>
 __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long q_geom_stride,
-    int QX, int QY, const R* __restrict__ lp, int bpg, int adjoint, const cpx<R>* __restrict__ twy)
+    int QX, int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
 {
     constexpr int NT = FusedShape<LY>::NT;
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
@@ -265,12 +292,14 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     const long long sstride = (long long)M * ny;
     cpx<R>* col = X + ((long long)b * S * M + kx) * ny;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+    Twiddles<R, LY> tw;
+    tw.load(g, twy, 1);
 
     for (int s = grp; s < S; s += NG) {
         const cpx<R>* src = col + s * sstride;
         cpx<R>* reg = sh + s * LY;
         wave_fft<R, LY, false>(
-            reg, g, twy, 1,
+            reg, g, tw,
             [&](int pos) -> cpx<R> { return pos < ny ? src[pos] : cpx<R>{R(0), R(0)}; },
             [&](int pos, cpx<R> v) { reg[pos] = v; });
     }
@@ -288,23 +317,33 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
         const int P = nz * (nz + 1) / 2;
         const long long colstride = (long long)P * 5 * QY;   // one kx column of the tensor
         const R* Qg = Q + (long long)geom * q_geom_stride;
-        const R one = R(1);
-        auto isc = [&](int l) -> R { return adjoint ? invt[l] : one; };
-        auto osc = [&](int l) -> R { return adjoint ? one : invt[l]; };
+        // sources scaled by 1/t for the transpose (T A T^-1), targets otherwise
+        auto isc = [&](int l) -> R { return invt[l]; };
         cpx<R> H[3 * NZMAX];
         auto store = [&](int ky) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int l = 0; l < NZMAX; ++l)
-                    if (l < nz) sh[(c * nz + l) * LY + ky] = cscale(H[c * NZMAX + l], osc(l));
+                    if (l < nz) {
+                        cpx<R> v = H[c * NZMAX + l];
+                        if constexpr (!ADJ) v = cscale(v, invt[l]);
+                        sh[(c * nz + l) * LY + ky] = v;
+                    }
+        };
+        auto ld = [&](int c, int l, int k) -> cpx<R> {
+            cpx<R> v = sh[(c * nz + l) * LY + k];
+            if constexpr (ADJ) v = cscale(v, isc(l));
+            return v;
         };
         const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);   // this lane's point
         const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);        // its quadrant column
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
+        const unsigned cbytes = (unsigned)(colstride * sizeof(R));
         if (kx != 0) {
-            auto in = [&](int c, int l) -> cpx<R> { return cscale(sh[(c * nz + l) * LY + ky], isc(l)); };
-            mix1<R, NZMAX>(nz, in, H, Qg + kx * colstride + kq, QY, sg, dg);
+            auto in = [&](int c, int l) -> cpx<R> { return ld(c, l, ky); };
+            const UniformBuf<R> qb(Qg + kx * colstride, cbytes);
+            mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg);
             store(ky);
         } else if (t != 0) {
             // column 0 holds Z = A + iB with A the kx = 0 and B the kx = Lx/2
@@ -313,12 +352,13 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             // W(t) = HA + i HB, W(-t) = conj(HA) + i conj(HB).
             const int k1 = t, k2 = LY - t;
             auto in = [&](int c, int l) -> cpx<R> {
-                const cpx<R> z1 = sh[(c * nz + l) * LY + k1], z2 = sh[(c * nz + l) * LY + k2];
-                const cpx<R> v = p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
-                                        : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
-                return cscale(v, isc(l));
+                const cpx<R> z1 = ld(c, l, k1), z2 = ld(c, l, k2);
+                return p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
+                              : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
             };
-            mix1<R, NZMAX>(nz, in, H, Qg + (p == 0 ? 0 : (long long)M * colstride) + t, QY, R(1), dg);
+            // rows kx = 0 and kx = M from one uniform base, the row in the lane offset
+            const UniformBuf<R> qb(Qg, (unsigned)((M + 1) * colstride * sizeof(R)));
+            mix1<R, NZMAX>(nz, in, H, qb, (unsigned)(t + (p == 0 ? 0 : M * colstride)), QY, R(1), dg);
 #pragma unroll
             for (int k = 0; k < 3 * NZMAX; ++k) {
                 const cpx<R> o = {__shfl_xor(H[k].x, 1), __shfl_xor(H[k].y, 1)};
@@ -330,10 +370,12 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             // ky = 0 (p = 0) or LY/2 (p = 1), each its own mirror: A = Re Z, B = Im Z
             const int kp = p == 0 ? 0 : LY / 2;
             cpx<R> HA[3 * NZMAX];
-            auto inA = [&](int c, int l) -> cpx<R> { return {sh[(c * nz + l) * LY + kp].x * isc(l), R(0)}; };
-            auto inB = [&](int c, int l) -> cpx<R> { return {sh[(c * nz + l) * LY + kp].y * isc(l), R(0)}; };
-            mix1<R, NZMAX>(nz, inA, HA, Qg + kp, QY, R(1), dg);
-            mix1<R, NZMAX>(nz, inB, H, Qg + (long long)M * colstride + kp, QY, R(1), dg);
+            auto inA = [&](int c, int l) -> cpx<R> { return {ld(c, l, kp).x, R(0)}; };
+            auto inB = [&](int c, int l) -> cpx<R> { return {ld(c, l, kp).y, R(0)}; };
+            const UniformBuf<R> q0(Qg, cbytes);
+            const UniformBuf<R> qM(Qg + (long long)M * colstride, cbytes);
+            mix1<R, NZMAX>(nz, inA, HA, q0, (unsigned)kp, QY, R(1), dg);
+            mix1<R, NZMAX>(nz, inB, H, qM, (unsigned)kp, QY, R(1), dg);
 #pragma unroll
             for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {HA[k].x - H[k].y, HA[k].y + H[k].x};
             store(kp);
@@ -345,7 +387,7 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
         cpx<R>* dst = col + s * sstride;
         cpx<R>* reg = sh + s * LY;
         wave_fft<R, LY, true>(
-            reg, g, twy, 1, [&](int pos) -> cpx<R> { return reg[pos]; },
+            reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
             [&](int pos, cpx<R> v) {
                 if (pos < ny) dst[pos] = v;
             });

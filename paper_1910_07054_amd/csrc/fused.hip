@@ -7,43 +7,53 @@ namespace hfd {
 namespace {
 constexpr size_t kMaxFusedLds = 163840;  // 160 KB of LDS per CU on gfx950
 
+// register budget: 1024-point columns run 16 waves per block (128 VGPRs),
+// which holds the accumulators of at most 4 layers
 template <typename R>
-int nzmax_for(int nz)
+int nzmax_for(int nz, int LY)
 {
-    if (sizeof(R) == 8) return nz <= 4 ? 4 : 0;
+    if (sizeof(R) == 8 || LY >= 1024) return nz <= 4 ? 4 : 0;
     return nz <= 4 ? 4 : (nz <= 8 ? 8 : (nz <= 12 ? 12 : 0));
+}
+
+template <typename R, int LY, int NZMAX, bool ADJ>
+hipError_t fused_a(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
+                   int QY, const void* lp, int bpg, const void* tw, hipStream_t s)
+{
+    const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
+    static bool attr_done = false;  // the attribute is set once to the largest possible size
+    if (lds > 65536 && !attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, B), dim3(FusedShape<LY>::NT), lds,
+                       s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QX, QY, (const R*)lp, bpg,
+                       (const cpx<R>*)tw);
+    return hipGetLastError();
 }
 
 template <typename R, int LY, int NZMAX>
 hipError_t fused_t(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
                    int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
 {
-    const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
-    static bool attr_done = false;  // the attribute is set once to the largest possible size
-    if (lds > 65536 && !attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_ymix_fused<R, LY, NZMAX>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
-    hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX>), dim3(M, B), dim3(FusedShape<LY>::NT), lds, s,
-                       (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QX, QY, (const R*)lp, bpg, adjoint,
-                       (const cpx<R>*)tw);
-    return hipGetLastError();
+    if (adjoint) return fused_a<R, LY, NZMAX, true>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, tw, s);
+    return fused_a<R, LY, NZMAX, false>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, tw, s);
 }
 
 template <typename R, int LY>
 hipError_t fused_nz(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
                     int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
 {
-    switch (nzmax_for<R>(nz)) {
+    switch (nzmax_for<R>(nz, LY)) {
     case 4: return fused_t<R, LY, 4>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
     case 8:
-        if constexpr (sizeof(R) == 4)
+        if constexpr (sizeof(R) == 4 && LY < 1024)
             return fused_t<R, LY, 8>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
         return hipErrorInvalidValue;
     case 12:
-        if constexpr (sizeof(R) == 4)
+        if constexpr (sizeof(R) == 4 && LY < 1024)
             return fused_t<R, LY, 12>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
@@ -74,7 +84,7 @@ bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
     const size_t lds = (fp64 ? 16 : 8) * 3 * (size_t)nz * LY;
     if (lds_bytes) *lds_bytes = lds;
     if (LY < 8 || LY > 1024) return false;
-    if ((fp64 ? nzmax_for<double>(nz) : nzmax_for<float>(nz)) == 0) return false;
+    if ((fp64 ? nzmax_for<double>(nz, LY) : nzmax_for<float>(nz, LY)) == 0) return false;
     return lds <= kMaxFusedLds;
 }
 

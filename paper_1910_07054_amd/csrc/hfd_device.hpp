@@ -45,6 +45,29 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Read-only view of `bytes` bytes at a wave-uniform base, loaded with raw buffer
+// instructions: a per-lane 32-bit byte offset plus a wave-uniform (scalar) byte
+// offset, so no per-lane 64-bit address arithmetic.  Loads beyond `bytes`
+// return zero instead of touching memory.
+template <typename R>
+struct UniformBuf {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ UniformBuf(const R* base, unsigned bytes)
+        : rsrc(__builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000))
+    {
+    }
+    // element at (scalar element offset s) + (lane element offset v)
+    __device__ __forceinline__ R ld(unsigned v, unsigned s) const
+    {
+        if constexpr (sizeof(R) == 4)
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(v * 4u),
+                                                                              (int)(s * 4u), 0));
+        else
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)(v * 8u),
+                                                                              (int)(s * 8u), 0));
+    }
+};
+
 // values per lane for a transform of length L
 __host__ __device__ constexpr int fft_vals(int L) { return L <= 8 ? L : (L <= 512 ? 8 : L / 64); }
 
@@ -105,21 +128,73 @@ __device__ __forceinline__ void dft(cpx<R>* v)
 
 // --- Stockham engine -------------------------------------------------------
 // X[k] = sum_n x[n] exp(-+2 pi i n k / L) (unnormalized in both directions).
-// tw: table of exp(-2 pi i m / (L * tws)) read at index m * tws, m in [0, L).
+// Twiddles: table of exp(-2 pi i m / (L * tws)) read at index m * tws,
+// m in [0, L).  A lane's twiddles depend only on its position g in the group,
+// so they are loaded once (Twiddles::load) and reused for every transform the
+// lane runs; inverse transforms use their conjugates.
 // load(pos) supplies x[pos] for the first pass; store(pos, v) receives X[pos]
 // from the last pass; sh is the group's LDS region of L values.
-template <typename R, int L, int V, bool INV, int NS, class Load, class Store>
-__device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g,
-                                         const cpx<R>* __restrict__ tw, int tws, Load& load,
-                                         Store& store)
+template <int L, int V, int NS>
+struct PassShape {
+    static constexpr int REM = L / NS;
+    static constexpr int RAD = (REM >= 8 && V % 8 == 0) ? 8 : ((REM >= 4 && V % 4 == 0) ? 4 : 2);
+    static constexpr int NB = V / RAD;
+    static constexpr bool LAST = (NS * RAD == L);
+    static constexpr int NEXT = LAST ? L : NS * RAD;
+};
+
+// twiddle registers of all passes after the first, in pass order
+template <int L, int V, int NS = 1>
+struct TwCount {
+    using P = PassShape<L, V, NS>;
+    static constexpr int here = NS > 1 ? P::NB * (P::RAD - 1) : 0;
+    static constexpr int value = here + (P::LAST ? 0 : TwCount<L, V, P::NEXT>::value);
+};
+template <int L, int V>
+struct TwCount<L, V, L> {
+    static constexpr int value = 0;
+};
+
+template <typename R, int L>
+struct Twiddles {
+    static constexpr int V = fft_vals(L);
+    static constexpr int GT = L / V;
+    static constexpr int N = TwCount<L, V>::value > 0 ? TwCount<L, V>::value : 1;
+    cpx<R> w[N];
+
+    template <int NS, int OFF>
+    __device__ __forceinline__ void fill(int g, const cpx<R>* __restrict__ tw, int tws)
+    {
+        using P = PassShape<L, V, NS>;
+        constexpr int here = NS > 1 ? P::NB * (P::RAD - 1) : 0;
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int u = 0; u < P::NB; ++u) {
+                const int j = g + GT * u;
+                const int k = j & (NS - 1);
+#pragma unroll
+                for (int r = 1; r < P::RAD; ++r)
+                    w[OFF + u * (P::RAD - 1) + r - 1] = tw[r * k * (L / (NS * P::RAD)) * tws];
+            }
+        }
+        if constexpr (!P::LAST) fill<P::NEXT, OFF + here>(g, tw, tws);
+    }
+    __device__ __forceinline__ void load(int g, const cpx<R>* __restrict__ tw, int tws)
+    {
+        fill<1, 0>(g, tw, tws);
+    }
+};
+
+template <typename R, int L, int V, bool INV, int NS, int OFF, class Load, class Store>
+__device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, const cpx<R>* w,
+                                         Load& load, Store& store)
 {
+    using P = PassShape<L, V, NS>;
     constexpr int GT = L / V;
-    constexpr int REM = L / NS;
-    constexpr int RAD = (REM >= 8 && V % 8 == 0) ? 8 : ((REM >= 4 && V % 4 == 0) ? 4 : 2);
-    constexpr int NB = V / RAD;
+    constexpr int RAD = P::RAD, NB = P::NB;
     constexpr int STRIDE = L / RAD;
     constexpr bool FIRST = (NS == 1);
-    constexpr bool LAST = (NS * RAD == L);
+    constexpr bool LAST = P::LAST;
     static_assert(L % (NS * RAD) == 0, "radix schedule");
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -133,14 +208,12 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g,
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-        const int j = g + GT * u;
         if constexpr (NS > 1) {
-            const int k = j & (NS - 1);
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                cpx<R> w = tw[r * k * (L / (NS * RAD)) * tws];
-                if (INV) w.y = -w.y;
-                v[u * RAD + r] = cmul(v[u * RAD + r], w);
+                cpx<R> t = w[OFF + u * (RAD - 1) + r - 1];
+                if (INV) t.y = -t.y;
+                v[u * RAD + r] = cmul(v[u * RAD + r], t);
             }
         }
         dft<R, RAD, INV>(&v[u * RAD]);
@@ -160,18 +233,30 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g,
     }
     if constexpr (!LAST) {
         wave_sync();
-        fft_pass<R, L, V, INV, NS * RAD>(v, sh, g, tw, tws, load, store);
+        constexpr int here = NS > 1 ? NB * (RAD - 1) : 0;
+        fft_pass<R, L, V, INV, P::NEXT, OFF + here>(v, sh, g, w, load, store);
     }
 }
 
+// One transform with preloaded twiddles.
 template <typename R, int L, bool INV, class Load, class Store>
-__device__ __forceinline__ void wave_fft(cpx<R>* sh, int g, const cpx<R>* __restrict__ tw, int tws,
-                                         Load load, Store store)
+__device__ __forceinline__ void wave_fft(cpx<R>* sh, int g, const Twiddles<R, L>& tw, Load load,
+                                         Store store)
 {
     constexpr int V = fft_vals(L);
     static_assert(L / V <= 64, "one transform must fit in a wavefront");
     cpx<R> v[V];
-    fft_pass<R, L, V, INV, 1>(v, sh, g, tw, tws, load, store);
+    fft_pass<R, L, V, INV, 1, 0>(v, sh, g, tw.w, load, store);
+}
+
+// One transform loading its own twiddles (single-use callers).
+template <typename R, int L, bool INV, class Load, class Store>
+__device__ __forceinline__ void wave_fft(cpx<R>* sh, int g, const cpx<R>* __restrict__ tw, int tws,
+                                         Load load, Store store)
+{
+    Twiddles<R, L> t;
+    t.load(g, tw, tws);
+    wave_fft<R, L, INV>(sh, g, t, load, store);
 }
 
 }  // namespace hfd
