@@ -119,6 +119,7 @@ def main():
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     inf = plan.info()
+    tune = plan.autotune(B)
     m = torch.from_numpy(wl.m.astype(np.float32)).to(dev)
     h = torch.empty_like(m)
     stream = torch.cuda.Stream()
@@ -210,6 +211,7 @@ def main():
         "err_vs_fp64_oracle": err,
         "stage_ms": stages,
         "setup_ms": setup_ms,
+        "autotune": tune,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

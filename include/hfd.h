@@ -59,13 +59,17 @@ typedef enum {
 enum {
     HFD_FP32 = 0,               /* FFTs and z-mixing in FP32 (tensor set up in FP64)   */
     HFD_FP64 = 1,               /* FFTs and z-mixing in FP64                           */
-    HFD_MIX_SPLIT_BF16 = 2,     /* z-mixing on MFMA with a three-way BF16 split of the
-                                   tensor and of the spectra, FP32 accumulation        */
+    HFD_MIX_SPLIT_BF16 = 2,     /* five-pass path, z-mixing of 16 states at a time on
+                                   MFMA with a three-way BF16 split of tensor and
+                                   spectra, FP32 accumulation (nz <= 8)                */
     HFD_SPLIT_PASSES = 4,       /* force the five-pass path (y-FFT, mix and inverse
                                    y-FFT as separate kernels) even where the fused
                                    y-pass fits in LDS                                  */
-    HFD_STORE_DTENSOR = 8       /* keep the thickness-derivative tensors resident
+    HFD_STORE_DTENSOR = 8,      /* keep the thickness-derivative tensors resident
                                    between hfd_demag_vjp calls (default: recompute)   */
+    HFD_MIX_BATCHED_FP32 = 16   /* five-pass path with the batched (16 states per
+                                   block) FP32 VALU mixing, the FP32 twin of
+                                   HFD_MIX_SPLIT_BF16                                 */
 };
 
 /*

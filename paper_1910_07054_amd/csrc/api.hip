@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_set>
@@ -43,7 +44,8 @@ hfd_status fail(hfd_status s, const std::string& msg)
 
 constexpr uint64_t kMagic = 0x31414c5044464848ull;
 constexpr uint64_t kDead = 0xdeaddeaddeaddeadull;
-constexpr unsigned kKnownFlags = HFD_FP64 | HFD_MIX_SPLIT_BF16 | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR;
+constexpr unsigned kKnownFlags =
+    HFD_FP64 | HFD_MIX_SPLIT_BF16 | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR | HFD_MIX_BATCHED_FP32;
 
 int next_pow2(long long v)
 {
@@ -87,15 +89,13 @@ struct hfd_plan_s {
     int nx = 0, ny = 0, nz = 0, G = 0, batch_max = 0;
     double dx = 0, dy = 0;
     unsigned flags = 0;
-    bool fp64 = false, bf16 = false, fused = false;
+    bool fp64 = false, bf16 = false, batched32 = false, fused = false;
     int Lx = 0, Ly = 0, M = 0, QX = 0, QY = 0, P = 0;
     size_t rsz = 4, csz = 8;
     std::vector<double> thick, zbot;  // [G][nz]
     // device
     void* Q = nullptr;          // [G][P][5][QX][QY]
     long long q_geom_stride = 0;
-    void* Qs = nullptr;         // split-BF16 operands (MFMA mixing)
-    long long qs_geom_stride = 0;
     void* lp = nullptr;         // [G][2][nz]
     void* twx = nullptr;        // plan precision, length Lx
     void* twy = nullptr;        // plan precision, length Ly
@@ -122,8 +122,11 @@ struct hfd_plan_s {
     int dchunk = 0;
     double* partial = nullptr;  // reduction partials [batch_max][nblk][2 nz]
     int nblk = 0;
-    // launch configuration chosen by the autotuner
-    int tuned = 0;
+    // field path: 0 fused y-pass, 1 five-pass generic mixing, 2 five-pass batched
+    // FP32 mixing, 3 five-pass split-BF16 MFMA mixing; default from the flags,
+    // per-batch choice from hfd_autotune
+    int path = 0;
+    std::map<int, int> tuned;
 };
 
 namespace {
@@ -204,14 +207,14 @@ void free_plan_memory(hfd_plan p)
 {
     if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
     if (p->twy == p->twy64) p->twy = nullptr;
-    void* bufs[] = {p->Q, p->Qs, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
+    void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
                     p->D, p->zidx, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
     p->dF = nullptr;
     p->dscale = nullptr;
-    p->Q = p->Qs = p->lp = p->twx = p->twy = p->X1 = p->Mh = p->Hh = nullptr;
+    p->Q = p->lp = p->twx = p->twy = p->X1 = p->Mh = p->Hh = nullptr;
     p->twx64 = p->twy64 = nullptr;
     p->D = nullptr;
     p->zidx = nullptr;
@@ -322,9 +325,6 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
             e = hipMemcpyAsync(p->lp, lf.data(), lf.size() * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
         }
-        if (e == hipSuccess && p->bf16)
-            e = launch_split_tensor((const float*)p->Q, p->Qs, p->G, p->nz, p->QX, p->QY,
-                                    (const float*)p->lp, 0, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
     } while (0);
@@ -494,13 +494,31 @@ hfd_status check_field_args(hfd_plan p, const void* a, const void* b, int batch,
     return HFD_OK;
 }
 
+int path_for(hfd_plan p, int batch)
+{
+    auto it = p->tuned.find(batch);
+    return it != p->tuned.end() ? it->second : p->path;
+}
+
+const char* path_name(int path)
+{
+    switch (path) {
+    case 0: return "fused";
+    case 1: return "five_pass";
+    case 2: return "five_pass_batched_fp32";
+    default: return "five_pass_bf16_mfma";
+    }
+}
+
 // Enqueue the field passes.  stage_ev: optional events recorded after each stage.
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
-                     hipEvent_t* stage_ev = nullptr, int* nstage = nullptr)
+                     hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1)
 {
     const int S = 3 * p->nz;
     const int nsig = batch * S;
     const int bpg = batch / p->G;
+    if (path < 0) path = path_for(p, batch);
+    if ((path == 2 || path == 3) && !mix_batched_supported(p->nz, batch, p->G)) path = 1;
     int k = 0;
     auto mark = [&]() {
         if (stage_ev) (void)hipEventRecord(stage_ev[k], s);
@@ -509,7 +527,7 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
                         nsig, p->twx, s));
     mark();
-    if (p->fused) {
+    if (path == 0) {
         HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, batch, p->Q,
                              p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
         mark();
@@ -517,12 +535,17 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
         const long long ncols = (long long)nsig * p->M;
         HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
         mark();
-        if (p->bf16)
-            HFD_HIP(launch_mix_bf16(p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Qs, p->qs_geom_stride,
-                                    p->QX, p->QY, p->lp, bpg, adjoint, s));
-        else
+        if (path == 2 || path == 3) {
+            // packed column by the generic kernel, the rest batched
             HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, s));
+                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1, s));
+            HFD_HIP(launch_mix_batched(path == 3, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                       p->q_geom_stride, p->QY, p->lp, bpg, adjoint, s));
+        } else {
+            HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, p->M,
+                                       s));
+        }
         mark();
         HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, p->X1, p->ny, ncols, p->twy, s));
         mark();
@@ -534,10 +557,14 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     return HFD_OK;
 }
 
-std::string stage_names(hfd_plan p)
+std::string stage_names(int path)
 {
-    if (p->fused) return "xfwd;ymix_fused;xinv";
-    return std::string("xfwd;yfwd;") + (p->bf16 ? "mix_bf16" : "mix") + ";yinv;xinv";
+    switch (path) {
+    case 0: return "xfwd;ymix_fused;xinv";
+    case 1: return "xfwd;yfwd;mix;yinv;xinv";
+    case 2: return "xfwd;yfwd;mix_batched_fp32;yinv;xinv";
+    default: return "xfwd;yfwd;mix_bf16_mfma;yinv;xinv";
+    }
 }
 
 }  // namespace
@@ -561,8 +588,10 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     if (batch_max < 1) return fail(HFD_EINVAL, "batch_max must be >= 1");
     if (batch_max < n_geom) return fail(HFD_EINVAL, "batch_max must be >= n_geom");
     if (flags & ~kKnownFlags) return fail(HFD_EINVAL, "unknown flag bits");
-    if ((flags & HFD_FP64) && (flags & HFD_MIX_SPLIT_BF16))
-        return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 requires the FP32 field path");
+    if ((flags & HFD_FP64) && (flags & (HFD_MIX_SPLIT_BF16 | HFD_MIX_BATCHED_FP32)))
+        return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 / HFD_MIX_BATCHED_FP32 require the FP32 field path");
+    if ((flags & HFD_MIX_SPLIT_BF16) && (flags & HFD_MIX_BATCHED_FP32))
+        return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 and HFD_MIX_BATCHED_FP32 are exclusive");
 
     hfd_plan p = new (std::nothrow) hfd_plan_s();
     if (!p) return fail(HFD_ENOMEM, "host allocation of the plan failed");
@@ -570,6 +599,7 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     p->dx = dx; p->dy = dy; p->flags = flags;
     p->fp64 = flags & HFD_FP64;
     p->bf16 = flags & HFD_MIX_SPLIT_BF16;
+    p->batched32 = flags & HFD_MIX_BATCHED_FP32;
     p->rsz = p->fp64 ? 8 : 4;
     p->csz = 2 * p->rsz;
     p->Lx = std::max(kMinL, next_pow2(2LL * nx));
@@ -580,7 +610,9 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     p->P = nz * (nz + 1) / 2;
     hfd_status st = validate_geometry(nz, n_geom, thickness, z_bottom, p->thick, p->zbot);
     if (st) { delete p; return st; }
-    p->fused = !(flags & HFD_SPLIT_PASSES) && !p->bf16 && fused_supported(p->fp64, p->Ly, nz, nullptr);
+    p->fused = !(flags & HFD_SPLIT_PASSES) && !p->bf16 && !p->batched32 &&
+               fused_supported(p->fp64, p->Ly, nz, nullptr);
+    p->path = p->fused ? 0 : (p->bf16 ? 3 : (p->batched32 ? 2 : 1));
 
     // sizes (overflow checked)
     const long long S = 3LL * nz;
@@ -615,11 +647,6 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         if (st) break;
         st = dev_alloc(&p->Hh, p->mh_bytes, "spectrum workspace");
         if (st) break;
-        if (p->bf16) {
-            p->qs_geom_stride = split_tensor_bytes(1, nz, p->QX, p->QY);
-            st = dev_alloc(&p->Qs, (size_t)split_tensor_bytes(n_geom, nz, p->QX, p->QY), "split tensor");
-            if (st) break;
-        }
         st = upload_twiddles(p, s);
         if (st) break;
         st = build_tensor(p, s);
@@ -745,7 +772,9 @@ hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int re
     for (int k = 0; k < 8; ++k) ms_per_stage[k] = k < ns ? acc[k] / reps : 0.0;
     *n_stages = ns;
     if (names && name_len > 0) {
-        std::string n = stage_names(p);
+        int path = path_for(p, batch);
+        if ((path == 2 || path == 3) && !mix_batched_supported(p->nz, batch, p->G)) path = 1;
+        std::string n = stage_names(path);
         std::snprintf(names, (size_t)name_len, "%s", n.c_str());
     }
     return HFD_OK;
@@ -754,10 +783,61 @@ hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int re
 hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int report_len)
 {
     HFD_TRY(check_plan(p));
-    (void)batch;
-    (void)stream;
-    if (report && report_len > 0)
-        std::snprintf(report, (size_t)report_len, "path=%s", p->fused ? "fused" : "split");
+    if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
+    if (batch % p->G) return fail(HFD_EINVAL, "batch must be a multiple of n_geom");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    hipStream_t s = (hipStream_t)stream;
+    // candidates: every compiled path valid for this plan; split-BF16 only when
+    // the plan was created with it (it changes the rounding of the mixing)
+    std::vector<int> cand;
+    if (!(p->flags & HFD_SPLIT_PASSES) && fused_supported(p->fp64, p->Ly, p->nz, nullptr)) cand.push_back(0);
+    cand.push_back(1);
+    if (!p->fp64 && mix_batched_supported(p->nz, batch, p->G)) {
+        cand.push_back(2);
+        if (p->bf16) cand.push_back(3);
+    }
+    const size_t bytes = (size_t)batch * 3 * p->nz * p->ny * p->nx * p->rsz;
+    void *m = nullptr, *h = nullptr;
+    HFD_TRY(dev_alloc(&m, bytes, "autotune input"));
+    hfd_status st = dev_alloc(&h, bytes, "autotune output");
+    if (st) { (void)hipFree(m); return st; }
+    hipEvent_t e0, e1;
+    std::string rep = "batch=" + std::to_string(batch);
+    int best = p->path;
+    double best_ms = 1e30;
+    do {
+        if (hipMemsetAsync(m, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            st = fail(HFD_EHIP, "autotune setup failed");
+            break;
+        }
+        for (int path : cand) {
+            for (int w = 0; w < 2 && st == HFD_OK; ++w) st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path);
+            const int reps = 10;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && st == HFD_OK; ++r) st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path);
+            (void)hipEventRecord(e1, s);
+            if (st) break;
+            if (hipEventSynchronize(e1) != hipSuccess) { st = fail(HFD_EHIP, "autotune sync failed"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double per = ms / reps;
+            char buf[96];
+            std::snprintf(buf, sizeof buf, " %s=%.4fms", path_name(path), per);
+            rep += buf;
+            if (per < best_ms) { best_ms = per; best = path; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(m);
+    (void)hipFree(h);
+    if (st) return st;
+    p->tuned[batch] = best;
+    rep += std::string(" -> ") + path_name(best);
+    if (report && report_len > 0) std::snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return HFD_OK;
 }
 

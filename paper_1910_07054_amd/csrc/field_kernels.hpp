@@ -213,35 +213,54 @@ __device__ __forceinline__ void block_apply(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, 
     hz.y = fma(xz, X.x, hz.y); hz.y = fma(yz, Y.x, hz.y); hz.y = fma(zz, Z.y, hz.y);
 }
 
+// Tensor values of one target row i (pairs (i, j), j >= i), 5 components each.
+template <typename R, int NZMAX>
+struct TensorRow {
+    R v[NZMAX][5];
+    // row i starts at pair index u = i nz - i (i - 1) / 2
+    __device__ __forceinline__ void load(const UniformBuf<R>& qcol, unsigned kq, int QY, int nz, int i)
+    {
+        const int u = i * nz - i * (i - 1) / 2;
+#pragma unroll
+        for (int j = 0; j < NZMAX; ++j)
+            if (j >= i && j < nz) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) v[j][c] = qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY));
+            }
+    }
+};
+
 // One frequency point: H_i += S^{ij} M_j and, for i < j, H_j += conj(S^{ij}) M_i.
 // qcol views the tensor from a wave-uniform base; kq is the lane's element
 // offset of its (kx row, quadrant ky); pair u, component c sits at
 // (u * 5 + c) * QY + kq.  sg is the sign of the ky-odd components (xy, yz).
+// Row i + 1 of the tensor is loaded while row i is applied; `first` holds
+// row 0, loaded by the caller ahead of time.
 template <typename R, int NZMAX, class In>
 __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
-                                     unsigned kq, int QY, R sg, const R* dg)
+                                     unsigned kq, int QY, R sg, const R* dg,
+                                     const TensorRow<R, NZMAX>& first)
 {
 #pragma unroll
     for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {R(0), R(0)};
-    int u = 0;
+    // double buffering needs two rows of registers; above 8 layers the rows
+    // are loaded one at a time
+    constexpr bool DB = NZMAX <= 8;
+    TensorRow<R, NZMAX> cur = first, nxt;
 #pragma unroll
     for (int i = 0; i < NZMAX; ++i) {
         if (i < nz) {
-            // tensor row i (pairs (i, j >= i)) loaded before use
-            R qv[NZMAX][5];
-#pragma unroll
-            for (int j = i; j < NZMAX; ++j)
-                if (j < nz) {
-#pragma unroll
-                    for (int c = 0; c < 5; ++c)
-                        qv[j][c] = qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY));
-                }
+            if constexpr (DB) {
+                if (i + 1 < NZMAX && i + 1 < nz) nxt.load(qcol, kq, QY, nz, i + 1);
+            } else if (i > 0) {
+                cur.load(qcol, kq, QY, nz, i);
+            }
             const cpx<R> ix = in(0, i), iy = in(1, i), iz = in(2, i);
 #pragma unroll
             for (int j = i; j < NZMAX; ++j) {
                 if (j < nz) {
-                    const R xx = qv[j][0], yy = qv[j][1], xy = sg * qv[j][2], xz = qv[j][3],
-                            yz = sg * qv[j][4];
+                    const R xx = cur.v[j][0], yy = cur.v[j][1], xy = sg * cur.v[j][2],
+                            xz = cur.v[j][3], yz = sg * cur.v[j][4];
                     R zz = -(xx + yy);
                     if (i == j) zz += dg[i];
                     if (i == j) {
@@ -256,9 +275,20 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
                     }
                 }
             }
-            u += nz - i;
+            if constexpr (DB) {
+                if (i + 1 < NZMAX) cur = nxt;
+            }
         }
     }
+}
+
+template <typename R, int NZMAX, class In>
+__device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
+                                     unsigned kq, int QY, R sg, const R* dg)
+{
+    TensorRow<R, NZMAX> first;
+    first.load(qcol, kq, QY, nz, 0);
+    mix1<R, NZMAX>(nz, in, H, qcol, kq, QY, sg, dg, first);
 }
 
 template <int LY>
@@ -295,6 +325,22 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     Twiddles<R, LY> tw;
     tw.load(g, twy, 1);
 
+    // lane -> frequency point of the mixing phase (see below); the first tensor
+    // row of an ordinary column is requested now so that its latency overlaps
+    // the forward transforms
+    const int t = tid >> 1, p = tid & 1;
+    const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);   // this lane's point
+    const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);        // its quadrant column
+    const int P = nz * (nz + 1) / 2;
+    const long long colstride = (long long)P * 5 * QY;       // one kx column of the tensor
+    const R* Qg = Q + (long long)geom * q_geom_stride;
+    const unsigned cbytes = (unsigned)(colstride * sizeof(R));
+    const UniformBuf<R> qb(Qg + kx * colstride, cbytes);
+    // (above 8 layers the registers do not hold a prefetched row)
+    TensorRow<R, NZMAX> row0;
+    if constexpr (NZMAX <= 8)
+        if (kx != 0 && t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0);
+
     for (int s = grp; s < S; s += NG) {
         const cpx<R>* src = col + s * sstride;
         cpx<R>* reg = sh + s * LY;
@@ -305,7 +351,6 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     }
     __syncthreads();
 
-    const int t = tid >> 1, p = tid & 1;
     if (t < LY / 2) {
         const R* lpg = lp + (long long)geom * 2 * nz;
         R invt[NZMAX], dg[NZMAX];
@@ -314,9 +359,6 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             invt[i] = i < nz ? lpg[i] : R(0);
             dg[i] = i < nz ? lpg[nz + i] : R(0);
         }
-        const int P = nz * (nz + 1) / 2;
-        const long long colstride = (long long)P * 5 * QY;   // one kx column of the tensor
-        const R* Qg = Q + (long long)geom * q_geom_stride;
         // sources scaled by 1/t for the transpose (T A T^-1), targets otherwise
         auto isc = [&](int l) -> R { return invt[l]; };
         cpx<R> H[3 * NZMAX];
@@ -336,14 +378,11 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             if constexpr (ADJ) v = cscale(v, isc(l));
             return v;
         };
-        const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);   // this lane's point
-        const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);        // its quadrant column
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
-        const unsigned cbytes = (unsigned)(colstride * sizeof(R));
         if (kx != 0) {
             auto in = [&](int c, int l) -> cpx<R> { return ld(c, l, ky); };
-            const UniformBuf<R> qb(Qg + kx * colstride, cbytes);
-            mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg);
+            if constexpr (NZMAX <= 8) mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg, row0);
+            else mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg);
             store(ky);
         } else if (t != 0) {
             // column 0 holds Z = A + iB with A the kx = 0 and B the kx = Lx/2
@@ -454,11 +493,12 @@ __global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ 
                                                      cpx<R>* __restrict__ Hh, int nz, int M, int LY,
                                                      const R* __restrict__ Q,
                                                      long long q_geom_stride, int QX, int QY,
-                                                     const R* __restrict__ lp, int bpg, int adjoint)
+                                                     const R* __restrict__ lp, int bpg, int adjoint,
+                                                     int kx0)
 {
     const int ky = blockIdx.x * blockDim.x + threadIdx.x;
     if (ky >= LY) return;
-    const int kx = blockIdx.y, b = blockIdx.z;
+    const int kx = kx0 + blockIdx.y, b = blockIdx.z;
     const int S = 3 * nz, geom = b / bpg;
     const long long sst = (long long)M * LY;
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;

@@ -29,18 +29,18 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
                         long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s);
 
+// generic mixing of the kx columns [kx0, kx0 + nkx)
 hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
                               const void* Q, long long q_geom_stride, int QX, int QY, const void* lp,
-                              int bpg, int adjoint, hipStream_t s);
+                              int bpg, int adjoint, int kx0, int nkx, hipStream_t s);
 
-// split-BF16 MFMA mixing on full spectra (FP32 path only)
-hipError_t launch_mix_bf16(const void* Mh, void* Hh, int nz, int M, int LY, int B, const void* Qs,
-                           long long qs_geom_stride, int QX, int QY, const void* lp, int bpg,
-                           int adjoint, hipStream_t s);
-// three-way BF16 split of an FP32 tensor into the MFMA operand layout
-hipError_t launch_split_tensor(const float* Q, void* Qs, int G, int nz, int QX, int QY,
-                               const float* lp, int Lxy_unused, hipStream_t s);
-long long split_tensor_bytes(int G, int nz, int QX, int QY);
+// batched mixing of the kx columns 1 .. M-1 (16 states per block): matrix cores
+// with the three-way BF16 split (mfma = true) or FP32 VALU on the same staging
+bool mix_batched_supported(int nz, int B, int G);
+size_t mix_batched_lds(int nz);
+hipError_t launch_mix_batched(bool mfma, const void* Mh, void* Hh, int nz, int M, int LY, int B,
+                              const void* Q, long long q_geom_stride, int QY, const void* lp, int bpg,
+                              int adjoint, hipStream_t s);
 
 // thickness-gradient reduction over the spectra (states b0 .. b0+nb-1)
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,

@@ -59,17 +59,18 @@ hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, 
 
 hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
                               const void* Q, long long qgs, int QX, int QY, const void* lp,
-                              int bpg, int adjoint, hipStream_t s)
+                              int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
 {
-    dim3 grid((LY + 255) / 256, M, B);
+    if (nkx <= 0) return hipSuccess;
+    dim3 grid((LY + 255) / 256, nkx, B);
     if (fp64)
         hipLaunchKernelGGL(k_mix_generic<double>, grid, dim3(256), 0, s, (const cpx<double>*)Mh,
                            (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs, QX, QY,
-                           (const double*)lp, bpg, adjoint);
+                           (const double*)lp, bpg, adjoint, kx0);
     else
         hipLaunchKernelGGL(k_mix_generic<float>, grid, dim3(256), 0, s, (const cpx<float>*)Mh,
                            (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QX, QY,
-                           (const float*)lp, bpg, adjoint);
+                           (const float*)lp, bpg, adjoint, kx0);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhfd.so")
 
 HFD_OK, HFD_EINVAL, HFD_ENOMEM, HFD_EHIP, HFD_EBATCH, HFD_EHANDLE, HFD_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 HFD_FP32, HFD_FP64, HFD_MIX_SPLIT_BF16, HFD_SPLIT_PASSES, HFD_STORE_DTENSOR = 0, 1, 2, 4, 8
+HFD_MIX_BATCHED_FP32 = 16
 
 STATUS_NAMES = {0: "HFD_OK", -1: "HFD_EINVAL", -2: "HFD_ENOMEM", -3: "HFD_EHIP", -4: "HFD_EBATCH",
                 -5: "HFD_EHANDLE", -6: "HFD_ENOTSUP"}

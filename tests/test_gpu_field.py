@@ -141,3 +141,56 @@ def test_adjoint_matches_oracle_transpose():
                                g[b].astype(np.float64), transpose=True)
             assert rel_err(gm[b], ref) < (1e-11 if fp64 else 1e-5)
         plan.destroy()
+
+
+# ---------------------------------------------------------------------------
+# Batched mixing (16 states per block): split-BF16 matrix cores and FP32 twin
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("flag", ["bf16", "fp32"])
+@pytest.mark.parametrize("case", [(24, 20, 4, 501, 20), (17, 33, 1, 502, 16), (20, 12, 8, 503, 33)],
+                         ids=lambda c: "x".join(map(str, c[:3])) + f"_B{c[4]}")
+def test_batched_mixing_matches_bruteforce(case, flag):
+    nx, ny, nz, seed, B = case
+    wl = W.small_case(nx, ny, nz, seed=seed, batch=B)
+    f = hfd.HFD_MIX_SPLIT_BF16 if flag == "bf16" else hfd.HFD_MIX_BATCHED_FP32
+    plan = plan_for(wl, flags=f)
+    assert not plan.info().fused
+    h, mused = run_field(plan, wl.m)
+    for b in (0, B // 2, B - 1):
+        ref = oracle.field(nx, ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
+        err = rel_err(h[b], ref)
+        assert err < 1e-5, (b, err)
+    plan.destroy()
+
+
+def test_batched_mixing_adjoint_and_stacks():
+    """Transpose through the batched kernels, two stacks of 16 states each."""
+    import torch
+    rng = np.random.default_rng(44)
+    nx, ny, nz, G = 12, 10, 3, 2
+    t = rng.uniform(0.5, 2.5, (G, nz))
+    zb = np.stack([W.stack_bottoms(t[g], [0.2, 0.0]) for g in range(G)])
+    g = rng.standard_normal((32, 3, nz, ny, nx)).astype(np.float32)
+    for f in (hfd.HFD_MIX_SPLIT_BF16, hfd.HFD_MIX_BATCHED_FP32):
+        plan = hfd.Plan(nx, ny, 2.0, 1.5, t, zb, batch_max=32, flags=f)
+        gm, _ = plan.vjp(None, torch.from_numpy(g).cuda(), want_m=True, want_t=False)
+        gm = gm.cpu().numpy().astype(np.float64)
+        for b in (0, 15, 16, 31):
+            k = b // 16
+            ref = oracle.field(nx, ny, 2.0, 1.5, zb[k], t[k], g[b].astype(np.float64), transpose=True)
+            assert rel_err(gm[b], ref) < 1e-5, (f, b)
+        plan.destroy()
+
+
+def test_autotune_keeps_results_correct():
+    """The autotuner times the valid paths, keeps the fastest for the batch,
+    and the field computed afterwards still matches the oracle."""
+    wl = W.small_case(40, 36, 3, seed=601, batch=16)
+    plan = plan_for(wl, flags=hfd.HFD_MIX_SPLIT_BF16 * 0)
+    rep = plan.autotune(16)
+    assert "->" in rep and "fused" in rep and "five_pass" in rep, rep
+    h, mused = run_field(plan, wl.m)
+    for b in (0, 15):
+        ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
+        assert rel_err(h[b], ref) < 1e-5
+    plan.destroy()

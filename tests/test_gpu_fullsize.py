@@ -36,11 +36,12 @@ def _field_full(wl, flags):
 
 
 @pytest.mark.parametrize("name,split", [("C2", False), ("M0", False), ("M0", True), ("C3", False),
-                                        ("C4", False), ("C5", False)])
+                                        ("C3", "bf16"), ("C3", "fp32"), ("C4", False), ("C5", False)])
 def test_sampled_cells_match_oracle(name, split):
     import torch
     wl = W.CONFIGS[name]()
-    flags = hfd.HFD_FP32 | (hfd.HFD_SPLIT_PASSES if split else 0)
+    flags = {False: hfd.HFD_FP32, True: hfd.HFD_SPLIT_PASSES, "bf16": hfd.HFD_MIX_SPLIT_BF16,
+             "fp32": hfd.HFD_MIX_BATCHED_FP32}[split]
     h, info = _field_full(wl, flags)
     g = np.load(os.path.join(GOLD, f"{name}_samples.npz"))
     s = torch.from_numpy(g["samples"].astype(np.int64)).cuda()
