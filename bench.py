@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--split", action="store_true", help="force the five-pass path")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time every mixing path (and 64 single-state calls) on the workload, "
+                         "each with its error against the stored oracle values")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -75,7 +78,7 @@ def cpu_baseline(wl, target_s=12.0):
     oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, samples=samples(n))
     t_n = time.perf_counter() - t0
     per = max((t_n - t_tab) / n, 1e-9)
-    n2 = int(min(4096, max(n, target_s / per)))
+    n2 = int(min(131072, max(n, target_s / per)))
     t0 = time.perf_counter()
     oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, samples=samples(n2))
     t_n2 = time.perf_counter() - t0
@@ -92,6 +95,73 @@ def cpu_baseline(wl, target_s=12.0):
                    f"{t_tab:.1f} s of pair tables for that layer; extrapolated to {cells} targets "
                    f"= {t_eval:.0f} s per evaluation (tables excluded)"),
     }
+
+
+def golden_error(wl, h):
+    """max |h - h_oracle| / max |h_oracle| over the stored oracle samples of
+    this workload (None if there are none)."""
+    gpath = os.path.join(ROOT, "tests", "golden", f"{wl.name}_samples.npz")
+    if not os.path.exists(gpath):
+        return None
+    g = np.load(gpath)
+    import torch
+    idx = [torch.as_tensor(a, device=h.device) for a in (g["state"], *g["samples"].T)]
+    got = h[idx[0], :, idx[1], idx[2], idx[3]].double().cpu().numpy()
+    return float(np.abs(got.astype(np.float64) - g["h"]).max() / g["hnorm_max"])
+
+
+def replay_ms(fn, steps, warmup, stream):
+    """Capture fn() into a HIP graph and time `steps` replays; ms per replay."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(max(warmup, 1)):
+            fn()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        fn()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def compare_paths(wl, m, steps, warmup, stream):
+    """Every field path on the same states: one plan per path, B states per
+    call, plus the plain single-state form (B calls of one state)."""
+    import torch
+    from paper_1910_07054_amd import hfd
+    B = wl.batch
+    res = {}
+    h = torch.empty_like(m)
+    plan1 = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=1, flags=hfd.HFD_FP32)
+
+    def single():
+        for b in range(B):
+            plan1.field(m[b:b + 1], out=h[b:b + 1], stream=stream)
+    ms = replay_ms(single, max(steps // 4, 5), warmup, stream)
+    res["single_state_fp32_fused"] = {"ms_per_batch": ms, "evals_per_s": B / (ms * 1e-3),
+                                      "err_vs_fp64_oracle": golden_error(wl, h)}
+    plan1.destroy()
+    variants = [("fused_fp32", hfd.HFD_FP32), ("five_pass_fp32", hfd.HFD_SPLIT_PASSES),
+                ("five_pass_batched_fp32", hfd.HFD_MIX_BATCHED_FP32),
+                ("five_pass_split_bf16_mfma", hfd.HFD_MIX_SPLIT_BF16)]
+    for name, fl in variants:
+        plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=B, flags=fl)
+        h.zero_()
+        ms = replay_ms(lambda: plan.field(m, out=h, stream=stream), steps, warmup, stream)
+        res[name] = {"ms_per_batch": ms, "evals_per_s": B / (ms * 1e-3),
+                     "err_vs_fp64_oracle": golden_error(wl, h),
+                     "stage_ms": plan.time_stages(m, h, reps=max(steps // 4, 5), stream=stream)}
+        plan.destroy()
+    base = res["single_state_fp32_fused"]["ms_per_batch"]
+    for v in res.values():
+        v["speedup_vs_single_state"] = base / v["ms_per_batch"]
+    return res
 
 
 def main():
@@ -171,15 +241,7 @@ def main():
     alg_bytes = algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly)
 
     # accuracy against stored oracle values for this workload, if present
-    err = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"{wl.name}_samples.npz")
-    if os.path.exists(gpath):
-        g = np.load(gpath)
-        s = g["samples"]
-        hh = h.cpu().numpy()
-        got = hh[g["state"], :, s[:, 0], s[:, 1], s[:, 2]]
-        ref = g["h"]
-        err = float(np.abs(got - ref).max() / g["hnorm_max"])
+    err = golden_error(wl, h)
 
     roof = None
     if dom_bytes is not None:
@@ -214,6 +276,8 @@ def main():
         "autotune": tune,
         "roofline": roof,
     }
+    if args.compare:
+        out["path_comparison"] = compare_paths(wl, m, args.steps, args.warmup, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     plan.destroy()

@@ -213,11 +213,29 @@ __device__ __forceinline__ void block_apply(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, 
     hz.y = fma(xz, X.x, hz.y); hz.y = fma(yz, Y.x, hz.y); hz.y = fma(zz, Z.y, hz.y);
 }
 
+// On the kx = 0 and kx = Lx/2 rows of the tensor xy and xz vanish (both are
+// odd in x, lateral parity); EDGE = 1 drops them.
+template <int EDGE, typename R>
+__device__ __forceinline__ void block_apply_e(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz, cpx<R> X, cpx<R> Y,
+                                              cpx<R> Z, R xx, R yy, R zz, R xy, R xz, R yz)
+{
+    if constexpr (EDGE == 0) {
+        block_apply(hx, hy, hz, X, Y, Z, xx, yy, zz, xy, xz, yz);
+    } else {
+        hx.x = fma(xx, X.x, hx.x); hx.y = fma(xx, X.y, hx.y);
+        hy.x = fma(yy, Y.x, hy.x); hy.x = fma(-yz, Z.y, hy.x);
+        hy.y = fma(yy, Y.y, hy.y); hy.y = fma(yz, Z.x, hy.y);
+        hz.x = fma(-yz, Y.y, hz.x); hz.x = fma(zz, Z.x, hz.x);
+        hz.y = fma(yz, Y.x, hz.y); hz.y = fma(zz, Z.y, hz.y);
+    }
+}
+
 // Tensor values of one target row i (pairs (i, j), j >= i), 5 components each.
 template <typename R, int NZMAX>
 struct TensorRow {
     R v[NZMAX][5];
     // row i starts at pair index u = i nz - i (i - 1) / 2
+    template <int EDGE = 0>
     __device__ __forceinline__ void load(const UniformBuf<R>& qcol, unsigned kq, int QY, int nz, int i)
     {
         const int u = i * nz - i * (i - 1) / 2;
@@ -225,7 +243,10 @@ struct TensorRow {
         for (int j = 0; j < NZMAX; ++j)
             if (j >= i && j < nz) {
 #pragma unroll
-                for (int c = 0; c < 5; ++c) v[j][c] = qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY));
+                for (int c = 0; c < 5; ++c) {
+                    const bool need = EDGE == 0 || c < 2 || c == 4;
+                    v[j][c] = need ? qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY)) : R(0);
+                }
             }
     }
 };
@@ -236,7 +257,7 @@ struct TensorRow {
 // (u * 5 + c) * QY + kq.  sg is the sign of the ky-odd components (xy, yz).
 // Row i + 1 of the tensor is loaded while row i is applied; `first` holds
 // row 0, loaded by the caller ahead of time.
-template <typename R, int NZMAX, class In>
+template <typename R, int NZMAX, int EDGE = 0, class In>
 __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
                                      unsigned kq, int QY, R sg, const R* dg,
                                      const TensorRow<R, NZMAX>& first)
@@ -251,9 +272,9 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
     for (int i = 0; i < NZMAX; ++i) {
         if (i < nz) {
             if constexpr (DB) {
-                if (i + 1 < NZMAX && i + 1 < nz) nxt.load(qcol, kq, QY, nz, i + 1);
+                if (i + 1 < NZMAX && i + 1 < nz) nxt.template load<EDGE>(qcol, kq, QY, nz, i + 1);
             } else if (i > 0) {
-                cur.load(qcol, kq, QY, nz, i);
+                cur.template load<EDGE>(qcol, kq, QY, nz, i);
             }
             const cpx<R> ix = in(0, i), iy = in(1, i), iz = in(2, i);
 #pragma unroll
@@ -264,14 +285,14 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
                     R zz = -(xx + yy);
                     if (i == j) zz += dg[i];
                     if (i == j) {
-                        block_apply(H[i], H[NZMAX + i], H[2 * NZMAX + i], ix, iy, iz, xx, yy, zz, xy,
-                                    xz, yz);
+                        block_apply_e<EDGE>(H[i], H[NZMAX + i], H[2 * NZMAX + i], ix, iy, iz, xx, yy,
+                                            zz, xy, xz, yz);
                     } else {
                         const cpx<R> jx = in(0, j), jy = in(1, j), jz = in(2, j);
-                        block_apply(H[i], H[NZMAX + i], H[2 * NZMAX + i], jx, jy, jz, xx, yy, zz, xy,
-                                    xz, yz);
-                        block_apply(H[j], H[NZMAX + j], H[2 * NZMAX + j], ix, iy, iz, xx, yy, zz, xy,
-                                    -xz, -yz);
+                        block_apply_e<EDGE>(H[i], H[NZMAX + i], H[2 * NZMAX + i], jx, jy, jz, xx, yy,
+                                            zz, xy, xz, yz);
+                        block_apply_e<EDGE>(H[j], H[NZMAX + j], H[2 * NZMAX + j], ix, iy, iz, xx, yy,
+                                            zz, xy, -xz, -yz);
                     }
                 }
             }
@@ -282,14 +303,85 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
     }
 }
 
-template <typename R, int NZMAX, class In>
+template <typename R, int NZMAX, int EDGE = 0, class In>
 __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
                                      unsigned kq, int QY, R sg, const R* dg)
 {
     TensorRow<R, NZMAX> first;
-    first.load(qcol, kq, QY, nz, 0);
-    mix1<R, NZMAX>(nz, in, H, qcol, kq, QY, sg, dg, first);
+    first.template load<EDGE>(qcol, kq, QY, nz, 0);
+    mix1<R, NZMAX, EDGE>(nz, in, H, qcol, kq, QY, sg, dg, first);
 }
+
+// The two points of the packed column that are their own mirror (ky = 0 and
+// LY/2) need four real mixings: A = Re Z with the kx = 0 row and B = Im Z with
+// the kx = M row, at both points.  With LY lanes for LY + 2 mixings they are
+// spread over the lanes of one wave: lane e takes one (point, part, target
+// layer i) and sums over the source layers.  All blocks there are diagonal
+// and real (xy, xz and yz vanish on those rows and columns).  qb0 views the
+// rows kx = 0 .. M of the tensor; lpg holds 1/t and the trace terms.  The
+// points are read by prep() and written by finish(), and no other lane touches
+// them.  prep() requests the operands (called before the lane's own mixing, so that
+// their latency overlaps it); finish() sums and writes the results.
+template <typename R, int LY, int NZMAX, bool ADJ>
+struct MirrorPoints {
+    R xx[NZMAX], yy[NZMAX], v[3][NZMAX];
+    int i, part, kp;
+    bool act;
+
+    __device__ __forceinline__ void prep(const cpx<R>* sh, int nz, int e, const UniformBuf<R>& qb0,
+                                         long long colstride, int M, int QY, const R* lpg)
+    {
+        i = e % NZMAX;
+        part = (e / NZMAX) & 1;
+        const int pt = e / (2 * NZMAX);
+        act = pt < 2 && i < nz;
+        const int ii = i < nz ? i : nz - 1;
+        kp = pt == 1 ? LY / 2 : 0;
+        const unsigned off = (unsigned)(kp + (part ? (long long)M * colstride : 0));
+#pragma unroll
+        for (int j = 0; j < NZMAX; ++j) {
+            const int jj = j < nz ? j : ii;
+            const int a = ii < jj ? ii : jj, b = ii < jj ? jj : ii;
+            // the pair index differs between lanes, so it goes into the lane
+            // offset (the second offset of a buffer load must be wave-uniform)
+            const unsigned o = off + (unsigned)((a * nz - a * (a - 1) / 2 + (b - a)) * 5 * QY);
+            xx[j] = qb0.ld(o, 0u);
+            yy[j] = qb0.ld(o + QY, 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < NZMAX; ++j) {
+            const int jj = j < nz ? j : 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const cpx<R> z = sh[(c * nz + jj) * LY + kp];
+                R x = part ? z.y : z.x;
+                if constexpr (ADJ) x *= lpg[jj];
+                v[c][j] = (act && j < nz) ? x : R(0);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void finish(cpx<R>* sh, int nz, const R* lpg)
+    {
+        wave_sync();  // the whole wave has read its operands
+        const int ii = i < nz ? i : nz - 1;
+        const R dgi = lpg[nz + ii];
+        R acc[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int j = 0; j < NZMAX; ++j) {
+            const R zz = (j == ii ? dgi : R(0)) - (xx[j] + yy[j]);
+            acc[0] = fma(xx[j], v[0][j], acc[0]);
+            acc[1] = fma(yy[j], v[1][j], acc[1]);
+            acc[2] = fma(zz, v[2][j], acc[2]);
+        }
+        if (act) {
+            const R sc = ADJ ? R(1) : lpg[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                reinterpret_cast<R*>(&sh[(c * nz + i) * LY + kp])[part] = acc[c] * sc;
+        }
+    }
+};
 
 template <int LY>
 struct FusedShape {
@@ -336,20 +428,52 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     const R* Qg = Q + (long long)geom * q_geom_stride;
     const unsigned cbytes = (unsigned)(colstride * sizeof(R));
     const UniformBuf<R> qb(Qg + kx * colstride, cbytes);
+    // packed column: rows kx = 0 and kx = M from one uniform base, the row in
+    // the lane offset
+    const UniformBuf<R> qb0(Qg, (unsigned)((M + 1) * colstride * sizeof(R)));
+    const unsigned off0 = (unsigned)(t + (p == 0 ? 0 : M * colstride));
     // (above 8 layers the registers do not hold a prefetched row)
     TensorRow<R, NZMAX> row0;
-    if constexpr (NZMAX <= 8)
-        if (kx != 0 && t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0);
+    if constexpr (NZMAX <= 8) {
+        if (kx != 0) {
+            if (t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0);
+        } else if (t != 0 && t < LY / 2) {
+            row0.template load<1>(qb0, off0, QY, nz, 0);
+        }
+    }
 
-    for (int s = grp; s < S; s += NG) {
-        const cpx<R>* src = col + s * sstride;
-        cpx<R>* reg = sh + s * LY;
-        wave_fft<R, LY, false>(
-            reg, g, tw,
-            [&](int pos) -> cpx<R> { return pos < ny ? src[pos] : cpx<R>{R(0), R(0)}; },
-            [&](int pos, cpx<R> v) { reg[pos] = v; });
+    // forward transforms: the inputs of all of this group's signals are
+    // requested first, then transformed one after the other
+    constexpr int NR = (3 * NZMAX + NG - 1) / NG;   // signals per group, at most
+    cpx<R> xin[NR][V];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int s = grp + r * NG;
+        if (s < S) {
+            const cpx<R>* src = col + s * sstride;
+            fft_first_loads<R, LY>(xin[r], g, [&](int pos) -> cpx<R> {
+                return pos < ny ? src[pos] : cpx<R>{R(0), R(0)};
+            });
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int s = grp + r * NG;
+        if (s < S) {
+            cpx<R>* reg = sh + s * LY;
+            wave_fft_pre<R, LY, false>(reg, g, tw, xin[r], [&](int pos, cpx<R> v) { reg[pos] = v; });
+        }
     }
     __syncthreads();
+
+    // ky = 0 and LY/2 of the packed column are mixed by the first wave; its
+    // operands are requested before the wave's own mixing where the register
+    // budget allows (up to 512 threads per block)
+    constexpr bool mirror_early = NT <= 512;
+    MirrorPoints<R, LY, NZMAX, ADJ> mirror;
+    const bool mirror_wave = kx == 0 && tid < 64;
+    if (mirror_early && mirror_wave)
+        mirror.prep(sh, nz, tid, qb0, colstride, M, QY, lp + (long long)geom * 2 * nz);
 
     if (t < LY / 2) {
         const R* lpg = lp + (long long)geom * 2 * nz;
@@ -395,9 +519,9 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
                 return p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
                               : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
             };
-            // rows kx = 0 and kx = M from one uniform base, the row in the lane offset
-            const UniformBuf<R> qb(Qg, (unsigned)((M + 1) * colstride * sizeof(R)));
-            mix1<R, NZMAX>(nz, in, H, qb, (unsigned)(t + (p == 0 ? 0 : M * colstride)), QY, R(1), dg);
+            // on the rows kx = 0 and kx = M only xx, yy, zz and yz are non-zero
+            if constexpr (NZMAX <= 8) mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg, row0);
+            else mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg);
 #pragma unroll
             for (int k = 0; k < 3 * NZMAX; ++k) {
                 const cpx<R> o = {__shfl_xor(H[k].x, 1), __shfl_xor(H[k].y, 1)};
@@ -405,20 +529,12 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
                 H[k] = p == 0 ? cpx<R>{A.x - Bv.y, A.y + Bv.x} : cpx<R>{A.x + Bv.y, Bv.x - A.y};
             }
             store(p == 0 ? k1 : k2);
-        } else {
-            // ky = 0 (p = 0) or LY/2 (p = 1), each its own mirror: A = Re Z, B = Im Z
-            const int kp = p == 0 ? 0 : LY / 2;
-            cpx<R> HA[3 * NZMAX];
-            auto inA = [&](int c, int l) -> cpx<R> { return {ld(c, l, kp).x, R(0)}; };
-            auto inB = [&](int c, int l) -> cpx<R> { return {ld(c, l, kp).y, R(0)}; };
-            const UniformBuf<R> q0(Qg, cbytes);
-            const UniformBuf<R> qM(Qg + (long long)M * colstride, cbytes);
-            mix1<R, NZMAX>(nz, inA, HA, q0, (unsigned)kp, QY, R(1), dg);
-            mix1<R, NZMAX>(nz, inB, H, qM, (unsigned)kp, QY, R(1), dg);
-#pragma unroll
-            for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {HA[k].x - H[k].y, HA[k].y + H[k].x};
-            store(kp);
         }
+    }
+    if (mirror_wave) {
+        if constexpr (!mirror_early)
+            mirror.prep(sh, nz, tid, qb0, colstride, M, QY, lp + (long long)geom * 2 * nz);
+        mirror.finish(sh, nz, lp + (long long)geom * 2 * nz);
     }
     __syncthreads();
 

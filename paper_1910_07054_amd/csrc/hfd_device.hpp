@@ -185,7 +185,7 @@ struct Twiddles {
     }
 };
 
-template <typename R, int L, int V, bool INV, int NS, int OFF, class Load, class Store>
+template <typename R, int L, int V, bool INV, int NS, int OFF, bool PRE = false, class Load, class Store>
 __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, const cpx<R>* w,
                                          Load& load, Store& store)
 {
@@ -202,8 +202,11 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
             const int pos = j + r * STRIDE;
-            if constexpr (FIRST) v[u * RAD + r] = load(pos);
-            else v[u * RAD + r] = sh[pos];
+            if constexpr (FIRST) {
+                if constexpr (!PRE) v[u * RAD + r] = load(pos);
+            } else {
+                v[u * RAD + r] = sh[pos];
+            }
         }
     }
 #pragma unroll
@@ -236,6 +239,31 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
         constexpr int here = NS > 1 ? NB * (RAD - 1) : 0;
         fft_pass<R, L, V, INV, P::NEXT, OFF + here>(v, sh, g, w, load, store);
     }
+}
+
+// The values a lane reads in the first pass, in register order, so that the
+// input of several transforms can be requested before any of them starts.
+template <typename R, int L, class Load>
+__device__ __forceinline__ void fft_first_loads(cpx<R> (&v)[fft_vals(L)], int g, Load load)
+{
+    constexpr int V = fft_vals(L), GT = L / V;
+    using P = PassShape<L, V, 1>;
+    constexpr int STRIDE = L / P::RAD;
+#pragma unroll
+    for (int u = 0; u < P::NB; ++u)
+#pragma unroll
+        for (int r = 0; r < P::RAD; ++r) v[u * P::RAD + r] = load(g + GT * u + r * STRIDE);
+}
+
+// One transform whose first-pass values are already in v (fft_first_loads).
+template <typename R, int L, bool INV, class Store>
+__device__ __forceinline__ void wave_fft_pre(cpx<R>* sh, int g, const Twiddles<R, L>& tw,
+                                             cpx<R> (&v)[fft_vals(L)], Store store)
+{
+    constexpr int V = fft_vals(L);
+    static_assert(L / V <= 64, "one transform must fit in a wavefront");
+    auto none = [](int) { return cpx<R>{R(0), R(0)}; };
+    fft_pass<R, L, V, INV, 1, 0, true>(v, sh, g, tw.w, none, store);
 }
 
 // One transform with preloaded twiddles.

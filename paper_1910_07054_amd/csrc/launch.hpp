@@ -34,10 +34,10 @@ hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M
                               const void* Q, long long q_geom_stride, int QX, int QY, const void* lp,
                               int bpg, int adjoint, int kx0, int nkx, hipStream_t s);
 
-// batched mixing of the kx columns 1 .. M-1 (16 states per block): matrix cores
-// with the three-way BF16 split (mfma = true) or FP32 VALU on the same staging
+// batched mixing of the kx columns 1 .. M-1 (all states of one stack per block,
+// 16 at a time): matrix cores with the three-way BF16 split (mfma = true) or
+// FP32 VALU on the same staging
 bool mix_batched_supported(int nz, int B, int G);
-size_t mix_batched_lds(int nz);
 hipError_t launch_mix_batched(bool mfma, const void* Mh, void* Hh, int nz, int M, int LY, int B,
                               const void* Q, long long q_geom_stride, int QY, const void* lp, int bpg,
                               int adjoint, hipStream_t s);

@@ -164,19 +164,20 @@ def test_batched_mixing_matches_bruteforce(case, flag):
 
 
 def test_batched_mixing_adjoint_and_stacks():
-    """Transpose through the batched kernels, two stacks of 16 states each."""
+    """Transpose through the batched kernels, three stacks of 7 states each
+    (chunks of 16 states never straddle two stacks)."""
     import torch
     rng = np.random.default_rng(44)
-    nx, ny, nz, G = 12, 10, 3, 2
+    nx, ny, nz, G, bpg = 12, 10, 3, 3, 7
     t = rng.uniform(0.5, 2.5, (G, nz))
     zb = np.stack([W.stack_bottoms(t[g], [0.2, 0.0]) for g in range(G)])
-    g = rng.standard_normal((32, 3, nz, ny, nx)).astype(np.float32)
+    g = rng.standard_normal((G * bpg, 3, nz, ny, nx)).astype(np.float32)
     for f in (hfd.HFD_MIX_SPLIT_BF16, hfd.HFD_MIX_BATCHED_FP32):
-        plan = hfd.Plan(nx, ny, 2.0, 1.5, t, zb, batch_max=32, flags=f)
+        plan = hfd.Plan(nx, ny, 2.0, 1.5, t, zb, batch_max=G * bpg, flags=f)
         gm, _ = plan.vjp(None, torch.from_numpy(g).cuda(), want_m=True, want_t=False)
         gm = gm.cpu().numpy().astype(np.float64)
-        for b in (0, 15, 16, 31):
-            k = b // 16
+        for b in (0, 6, 7, 13, 14, 20):
+            k = b // bpg
             ref = oracle.field(nx, ny, 2.0, 1.5, zb[k], t[k], g[b].astype(np.float64), transpose=True)
             assert rel_err(gm[b], ref) < 1e-5, (f, b)
         plan.destroy()
