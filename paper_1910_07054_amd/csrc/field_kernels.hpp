@@ -49,6 +49,89 @@ struct XPassShape {
 // A length-LX real transform is one complex transform of length LX/2 on
 // z[n] = x[2n] + i x[2n+1] followed by the even/odd split.
 // ---------------------------------------------------------------------------
+// Split of the packed real transform, per row: lane g of the row's group owns
+// the frequency pairs (k, M - k) for k = g + GT i, i < KI; their twiddles
+// exp(-2 pi i k / LX) are loaded once per lane (for the longest rows, whose
+// transform needs the registers, they are read where used).
+template <typename R, int LX>
+struct RealSplit {
+    static constexpr int M = LX / 2, GT = XPassShape<R, LX>::GT, HM = M / 2 + 1;
+    static constexpr int KI = (HM + GT - 1) / GT;
+    static constexpr bool CACHE = KI * sizeof(R) <= 32;
+    cpx<R> w[CACHE ? KI : 1];
+    const cpx<R>* tw;
+    __device__ __forceinline__ void load(int g, const cpx<R>* __restrict__ twx)
+    {
+        tw = twx;
+        if constexpr (CACHE) {
+#pragma unroll
+            for (int i = 0; i < KI; ++i) {
+                const int k = g + GT * i;
+                w[i] = k < HM ? twx[k] : cpx<R>{R(0), R(0)};
+            }
+        }
+    }
+    __device__ __forceinline__ cpx<R> wk(int i, int k) const
+    {
+        if constexpr (CACHE) return w[i];
+        else return tw[k];
+    }
+    // forward: complex spectrum Z of z[n] = x[2n] + i x[2n+1] -> X[k], k < M,
+    // with X[0] and X[M] packed as X[0] + i X[M]
+    __device__ __forceinline__ void forward(cpx<R>* row, int g) const
+    {
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+            const int k = g + GT * i;
+            if (k >= HM) continue;
+            if (k == 0) {
+                const cpx<R> z = row[0];
+                row[0] = {z.x + z.y, z.x - z.y};
+            } else if (2 * k == M) {
+                row[k] = cconj(row[k]);
+            } else {
+                const cpx<R> a = row[k], b = row[M - k];
+                const cpx<R> E = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+                const cpx<R> O = {R(0.5) * (a.y + b.y), R(0.5) * (b.x - a.x)};
+                const cpx<R> wO = cmul(wk(i, k), O);
+                row[k] = cadd(E, wO);
+                row[M - k] = cconj(csub(E, wO));
+            }
+        }
+    }
+    // inverse: packed half spectrum -> spectrum of z (unnormalized, twice the
+    // forward's input)
+    __device__ __forceinline__ void inverse(cpx<R>* row, int g) const
+    {
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+            const int k = g + GT * i;
+            if (k >= HM) continue;
+            if (k == 0) {
+                const cpx<R> z = row[0];
+                row[0] = {z.x + z.y, z.x - z.y};
+            } else if (2 * k == M) {
+                const cpx<R> z = row[k];
+                row[k] = {R(2) * z.x, R(-2) * z.y};
+            } else {
+                const cpx<R> a = row[k], b = row[M - k];
+                const cpx<R> P = {a.x + b.x, a.y - b.y};   // a + conj(b)
+                const cpx<R> Qd = {a.x - b.x, a.y + b.y};  // a - conj(b)
+                const cpx<R> T = cmul(cconj(wk(i, k)), Qd);
+                row[k] = {P.x - T.y, P.y + T.x};
+                row[M - k] = {P.x + T.y, T.x - P.y};
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// x pass, forward: each row of nx reals (zero padded to LX) -> packed half
+// spectrum of LX/2 complex values, written transposed (y fastest).
+// A length-LX real transform is one complex transform of length LX/2 on
+// z[n] = x[2n] + i x[2n+1] followed by the even/odd split, which the row's
+// group applies to its own row.
+// ---------------------------------------------------------------------------
 template <typename R, int LX>
 __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
                                               int nx, int ny, long long in_sig_stride,
@@ -64,6 +147,8 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __res
     const R* base = in + (long long)sig * in_sig_stride;
     Twiddles<R, M> tw;
     tw.load(g, twx, 2);
+    RealSplit<R, LX> split;
+    split.load(g, twx);
 
     for (int r = grp; r < TY; r += NG) {
         const int y = y0 + r;
@@ -87,26 +172,8 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __res
                 },
                 [&](int pos, cpx<R> v) { row[pos] = v; });
         }
-    }
-    __syncthreads();
-    constexpr int HM = M / 2 + 1;
-    for (int idx = tid; idx < TY * HM; idx += NT) {
-        const int r = idx / HM, k = idx - r * HM;
-        if (y0 + r >= ny) continue;
-        cpx<R>* row = sh + r * RS;
-        if (k == 0) {
-            const cpx<R> z = row[0];
-            row[0] = {z.x + z.y, z.x - z.y};
-        } else if (2 * k == M) {
-            row[k] = cconj(row[k]);
-        } else {
-            const cpx<R> a = row[k], b = row[M - k];
-            const cpx<R> E = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
-            const cpx<R> O = {R(0.5) * (a.y + b.y), R(0.5) * (b.x - a.x)};
-            const cpx<R> wO = cmul(twx[k], O);
-            row[k] = cadd(E, wO);
-            row[M - k] = cconj(csub(E, wO));
-        }
+        wave_sync();
+        split.forward(row, g);
     }
     __syncthreads();
     cpx<R>* dst = out + (long long)sig * M * ny;
@@ -136,31 +203,12 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xinv(const cpx<R>* 
     const cpx<R>* src = in + (long long)sig * M * ny;
     Twiddles<R, M> tw;
     tw.load(g, twx, 2);
+    RealSplit<R, LX> split;
+    split.load(g, twx);
     for (int idx = tid; idx < M * TY; idx += NT) {
         const int r = idx % TY, kx = idx / TY;
         const int y = y0 + r;
         sh[r * RS + kx] = (y < ny) ? src[(long long)kx * ny + y] : cpx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    constexpr int HM = M / 2 + 1;
-    for (int idx = tid; idx < TY * HM; idx += NT) {
-        const int r = idx / HM, k = idx - r * HM;
-        if (y0 + r >= ny) continue;
-        cpx<R>* row = sh + r * RS;
-        if (k == 0) {
-            const cpx<R> z = row[0];
-            row[0] = {z.x + z.y, z.x - z.y};
-        } else if (2 * k == M) {
-            const cpx<R> z = row[k];
-            row[k] = {R(2) * z.x, R(-2) * z.y};
-        } else {
-            const cpx<R> a = row[k], b = row[M - k];
-            const cpx<R> P = {a.x + b.x, a.y - b.y};   // a + conj(b)
-            const cpx<R> Qd = {a.x - b.x, a.y + b.y};  // a - conj(b)
-            const cpx<R> T = cmul(cconj(twx[k]), Qd);
-            row[k] = {P.x - T.y, P.y + T.x};
-            row[M - k] = {P.x + T.y, T.x - P.y};
-        }
     }
     __syncthreads();
     R* obase = out + (long long)sig * out_sig_stride;
@@ -168,6 +216,8 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xinv(const cpx<R>* 
         const int y = y0 + r;
         if (y >= ny) break;
         cpx<R>* row = sh + r * RS;
+        split.inverse(row, g);
+        wave_sync();
         R* dst = obase + (long long)y * out_row_stride;
         if ((nx & 1) == 0 && (out_row_stride & 1) == 0) {
             cpx<R>* dst2 = reinterpret_cast<cpx<R>*>(dst);
