@@ -1,5 +1,6 @@
 // Instances of the FP64 tensor-setup kernels.
 #include "launch.hpp"
+#include <algorithm>
 #include "tensor_kernels.hpp"
 
 namespace hfd {
@@ -41,6 +42,22 @@ hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scal
     else
         hipLaunchKernelGGL(k_pack<float>, dim3((unsigned)nb), dim3(256), 0, s,
                            (const cpx<double>*)F, (float*)Q, scale, npairs, comps, M, Ly, QX, QY, pair0, pair_total);
+    return hipGetLastError();
+}
+
+// Zero n doubles with a kernel (used instead of a memset node on paths that a
+// caller may capture in a graph).
+__global__ __launch_bounds__(256) void k_zero64(double* __restrict__ p, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+hipError_t launch_zero64(double* p, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
