@@ -130,18 +130,25 @@ hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, voi
 hfd_status hfd_demag_vjp(hfd_plan plan, const void *m, const void *grad_h, void *grad_m,
                          double *grad_thickness, int batch, void *stream);
 
-/* Time each kernel stage of hfd_demag_field with HIP events over `reps`
- * launches on `stream` (inputs as for hfd_demag_field).  ms_per_stage[k]
- * receives the average duration of stage k (host array of length 8); n_stages
- * and names (semicolon separated, host buffer of name_len bytes) describe the
- * stages.  For measurement only; it synchronizes the stream. */
+/* Time each kernel stage of hfd_demag_field (inputs as for hfd_demag_field):
+ * one full evaluation, then the kernels of each stage launched `reps` times
+ * back to back between two HIP events on `stream`.  ms_per_stage[k] receives
+ * the average time per launch of stage k (host array of length 8); n_stages and
+ * names (semicolon separated, host buffer of name_len bytes) describe the
+ * stages.  Repeated stages run on their own output, so h holds unspecified
+ * values afterwards.  For measurement only; it synchronizes the stream. */
 hfd_status hfd_time_stages(hfd_plan plan, const void *m, void *h, int batch, int reps,
                            void *stream, double *ms_per_stage, int *n_stages, char *names,
                            int name_len);
 
-/* Measure the candidate launch shapes of the current path for `batch` states
- * (scratch data, HIP events) and keep the fastest per stage in the plan.
- * Returns the chosen configuration as text in `report` (host buffer). */
+/* Time every field path the plan can run for `batch` states (the fused
+ * y-pass where it fits in LDS, the five-pass path with generic mixing, the
+ * batched FP32 mixing for nz <= 8 and batch >= 16, the split-BF16 matrix-core
+ * mixing when the plan was created with HFD_MIX_SPLIT_BF16) on zero input and
+ * keep the fastest for this batch size; later calls with that batch use it.
+ * Allocates and frees a scratch input/output pair and synchronizes the stream,
+ * so it must not be captured in a graph.  `report` (host buffer) receives the
+ * timings and the choice as text, e.g. "batch=1 fused=0.047ms ... -> fused". */
 hfd_status hfd_autotune(hfd_plan plan, int batch, void *stream, char *report, int report_len);
 
 /* Plan description (host). */

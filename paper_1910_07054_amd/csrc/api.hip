@@ -511,8 +511,10 @@ const char* path_name(int path)
 }
 
 // Enqueue the field passes.  stage_ev: optional events recorded after each stage.
+// `only` >= 0 launches the kernels of that stage alone (stage timing).
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
-                     hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1)
+                     hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1,
+                     int only = -1)
 {
     const int S = 3 * p->nz;
     const int nsig = batch * S;
@@ -524,34 +526,41 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
         if (stage_ev) (void)hipEventRecord(stage_ev[k], s);
         ++k;
     };
-    HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
-                        nsig, p->twx, s));
+    auto on = [&]() { return only < 0 || only == k; };
+    if (on())
+        HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+                            nsig, p->twx, s));
     mark();
     if (path == 0) {
-        HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, batch, p->Q,
-                             p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
+        if (on())
+            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, batch, p->Q,
+                                 p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
         mark();
     } else {
         const long long ncols = (long long)nsig * p->M;
-        HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
+        if (on()) HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
         mark();
-        if (path == 2 || path == 3) {
-            // packed column by the generic kernel, the rest batched
-            HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1, s));
-            HFD_HIP(launch_mix_batched(path == 3, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                       p->q_geom_stride, p->QY, p->lp, bpg, adjoint, s));
-        } else {
-            HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                       p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, p->M,
-                                       s));
+        if (on()) {
+            if (path == 2 || path == 3) {
+                // packed column by the generic kernel, the rest batched
+                HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                           p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1,
+                                           s));
+                HFD_HIP(launch_mix_batched(path == 3, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                           p->q_geom_stride, p->QY, p->lp, bpg, adjoint, s));
+            } else {
+                HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
+                                           p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0,
+                                           p->M, s));
+            }
         }
         mark();
-        HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, p->X1, p->ny, ncols, p->twy, s));
+        if (on()) HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, p->X1, p->ny, ncols, p->twy, s));
         mark();
     }
-    HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
-                        nsig, p->twx, s));
+    if (on())
+        HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+                            nsig, p->twx, s));
     mark();
     if (nstage) *nstage = k;
     return HFD_OK;
@@ -751,25 +760,31 @@ hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int re
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t ev[9];
-    for (int k = 0; k < 9; ++k) HFD_HIP(hipEventCreate(&ev[k]));
-    double acc[8] = {0};
-    int ns = 0;
-    hfd_status st = HFD_OK;
-    for (int r = 0; r < reps && st == HFD_OK; ++r) {
-        (void)hipEventRecord(ev[0], s);
-        st = run_field(p, m, h, batch, 0, s, ev + 1, &ns);
-        if (st) break;
-        if (hipEventSynchronize(ev[ns]) != hipSuccess) { st = fail(HFD_EHIP, "event sync failed"); break; }
-        for (int k = 0; k < ns; ++k) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-            acc[k] += ms;
-        }
+    hipEvent_t e0, e1;
+    HFD_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(HFD_EHIP, "hipEventCreate failed");
     }
-    for (int k = 0; k < 9; ++k) (void)hipEventDestroy(ev[k]);
+    int ns = 0;
+    // one full evaluation fills the intermediate buffers; then each stage's
+    // kernels run `reps` times back to back between two events
+    hfd_status st = run_field(p, m, h, batch, 0, s, nullptr, &ns);
+    for (int k = 0; k < ns && st == HFD_OK; ++k) {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == HFD_OK; ++r)
+            st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, -1, k);
+        (void)hipEventRecord(e1, s);
+        if (st) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(HFD_EHIP, "event sync failed"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_per_stage[k] = (double)ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) return st;
-    for (int k = 0; k < 8; ++k) ms_per_stage[k] = k < ns ? acc[k] / reps : 0.0;
+    for (int k = ns; k < 8; ++k) ms_per_stage[k] = 0.0;
     *n_stages = ns;
     if (names && name_len > 0) {
         int path = path_for(p, batch);
@@ -793,7 +808,9 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     std::vector<int> cand;
     if (!(p->flags & HFD_SPLIT_PASSES) && fused_supported(p->fp64, p->Ly, p->nz, nullptr)) cand.push_back(0);
     cand.push_back(1);
-    if (!p->fp64 && mix_batched_supported(p->nz, batch, p->G)) {
+    // the batched kernels apply each frequency matrix to 16 states at a time;
+    // below that they are not worth timing
+    if (!p->fp64 && batch >= 16 && mix_batched_supported(p->nz, batch, p->G)) {
         cand.push_back(2);
         if (p->bf16) cand.push_back(3);
     }
