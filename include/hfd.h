@@ -67,9 +67,15 @@ enum {
                                    y-pass fits in LDS                                  */
     HFD_STORE_DTENSOR = 8,      /* keep the thickness-derivative tensors resident
                                    between hfd_demag_vjp calls (default: recompute)   */
-    HFD_MIX_BATCHED_FP32 = 16   /* five-pass path with the batched (16 states per
+    HFD_MIX_BATCHED_FP32 = 16,  /* five-pass path with the batched (16 states per
                                    block) FP32 VALU mixing, the FP32 twin of
                                    HFD_MIX_SPLIT_BF16                                 */
+    HFD_EQUIDISTANT = 32        /* equidistant stack (all thicknesses equal, uniform
+                                   pitch z_bottom[l+1] - z_bottom[l], n_geom = 1):
+                                   the layer sum by FFT along z as well (eq. FFT_3D,
+                                   Sec. 3.1), the method the paper compares with;
+                                   FP32 or FP64, no other flag; hfd_demag_vjp
+                                   supports grad_m only                               */
 };
 
 /*
@@ -87,8 +93,9 @@ enum {
  *               dy, nz; a batch of B states is split into n_geom equal runs
  *               and run g uses stack g (B must be a multiple of n_geom)
  *   batch_max   largest batch later passed to hfd_demag_field / _vjp
- *   flags       HFD_FP32 or HFD_FP64, optionally | HFD_MIX_SPLIT_BF16 (FP32
- *               only) | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR
+ *   flags       HFD_FP32 or HFD_FP64, optionally | HFD_MIX_SPLIT_BF16 or
+ *               HFD_MIX_BATCHED_FP32 (FP32 only) | HFD_SPLIT_PASSES |
+ *               HFD_STORE_DTENSOR; or HFD_EQUIDISTANT alone (with FP32/FP64)
  *   stream      HIP stream for the setup kernels; the call returns after the
  *               setup has completed on that stream
  *
@@ -160,6 +167,8 @@ typedef struct {
     int mix_bf16;           /* 1 if the z-mixing runs on split-BF16 MFMA           */
     long long tensor_bytes; /* bytes of the stored Fourier tensor (all stacks)     */
     long long work_bytes;   /* bytes of the field workspace                        */
+    int equidistant;        /* 1 for an HFD_EQUIDISTANT plan                       */
+    int Lz;                 /* padded length along z (equidistant plans), else 0   */
 } hfd_info;
 hfd_status hfd_get_info(hfd_plan plan, hfd_info *info);
 
@@ -169,7 +178,10 @@ hfd_status hfd_get_info(hfd_plan plan, hfd_info *info);
  * unique pairs i <= j in row-major upper-triangle order, components
  * (xx, yy, xy, xz, yz) of t_i * (-DFT2(N^{ij}) / (Lx Ly)); real parts for
  * xx, yy, xy, imaginary parts for xz, yz (the only non-zero parts by
- * lateral parity); zz follows from the trace (see DESIGN notes). */
+ * lateral parity); zz follows from the trace of the self-pair block.
+ * HFD_EQUIDISTANT plans: layout [Lx/2+1][Lz/2+1][6][Ly/2+1] (kx, kz,
+ * component, ky), components (xx, yy, zz, xy, xz, yz) of
+ * -DFT3(N) / (Lx Ly Lz), which are real by parity (eq. FFT_3D). */
 hfd_status hfd_export_fourier_tensor(hfd_plan plan, int geom, void *dst, long long dst_bytes);
 
 /* Compute the real-space FP64 tensor N^{ij}(p, q) of stack `geom` for one

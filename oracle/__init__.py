@@ -14,6 +14,8 @@ Parts:
   * ``fft_field``: the hybrid algorithm of Sec. 3.1 (2D discrete Fourier
     transform in x and y, explicit sum over layers in z), written with
     numpy's FFT as the library step, in FP64.
+  * ``fft3_field`` / ``fourier_tensor3``: the equidistant case of Sec. 3.1
+    (eq. FFT_3D, three-dimensional transform), same library step.
   * ``quad_tensor``: Gauss-Legendre quadrature of the cell-averaged dipole
     kernel, an independent route to the tensor of two disjoint cuboids.
 """
@@ -253,6 +255,57 @@ def fft_field(nx, ny, dx, dy, zbot, thick, m, Ntil=None, transpose=False) -> np.
                 else:
                     hh[:, i] -= np.einsum("yxkl,lyx->kyx", N33[i, j], mh[:, j])
         out[b] = np.real(np.fft.ifft2(hh))[:, :, :ny, :nx]
+    return out if batched else out[0]
+
+
+# --------------------------------------------------------------------------
+# Equidistant case (eq. FFT_3D of Sec. 3.1): transform along z as well
+# --------------------------------------------------------------------------
+def _pow2_at_least(n: int) -> int:
+    L = 1
+    while L < n:
+        L *= 2
+    return L
+
+
+def fourier_tensor3(nx, ny, dx, dy, nz, thick, pitch, Lx=None, Ly=None, Lz=None):
+    """3-D DFT (numpy) of the tensor of equal cells of thickness `thick` on a
+    regular z grid of `pitch`: the layer-offset tables N(p, q, d), d in
+    [-(nz-1), nz-1] (target minus source, Z = d * pitch), placed on an
+    Lx x Ly x Lz periodic grid; complex array [6][Lz][Ly][Lx]."""
+    Lx = Lx or 2 * nx
+    Ly = Ly or 2 * ny
+    Lz = Lz or max(2, _pow2_at_least(2 * nz))
+    if Lx < 2 * nx - 1 or Ly < 2 * ny - 1 or Lz < 2 * nz - 1:
+        raise ValueError("padded length too short for an aperiodic convolution")
+    grid = np.zeros((6, Lz, Ly, Lx))
+    py = np.arange(-(ny - 1), ny) % Ly
+    px = np.arange(-(nx - 1), nx) % Lx
+    for d in range(-(nz - 1), nz):
+        zt = d * pitch
+        tab = pair_table(nx, ny, dx, dy, zt, zt + thick, 0.0, thick)
+        grid[:, d % Lz, py[:, None], px[None, :]] = tab
+    return np.fft.fftn(grid, axes=(1, 2, 3))
+
+
+def fft3_field(nx, ny, dx, dy, thick, pitch, m, Ntil3=None) -> np.ndarray:
+    """h_k = -sum_l F^-1[F(N_kl) F(m_l)] with F the 3-D DFT (eq. FFT_3D), for
+    nz equal layers of thickness `thick` at bottoms z_i = i * pitch, FP64.
+    m: [3][nz][ny][nx] (or [B][3][nz][ny][nx]); returns the same shape."""
+    mm = np.asarray(m, dtype=np.float64)
+    batched = mm.ndim == 5
+    if not batched:
+        mm = mm[None]
+    nz = mm.shape[2]
+    if Ntil3 is None:
+        Ntil3 = fourier_tensor3(nx, ny, dx, dy, nz, thick, pitch)
+    Lz, Ly, Lx = Ntil3.shape[1:]
+    N33 = full3x3(np.moveaxis(Ntil3, 0, -1))          # [Lz][Ly][Lx][3][3]
+    out = np.empty_like(mm)
+    for b in range(mm.shape[0]):
+        mh = np.fft.fftn(mm[b], s=(Lz, Ly, Lx), axes=(1, 2, 3))   # [3][Lz][Ly][Lx]
+        hh = -np.einsum("zyxkl,lzyx->kzyx", N33, mh)
+        out[b] = np.real(np.fft.ifftn(hh, axes=(1, 2, 3)))[:, :nz, :ny, :nx]
     return out if batched else out[0]
 
 

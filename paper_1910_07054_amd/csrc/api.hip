@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -45,7 +46,8 @@ hfd_status fail(hfd_status s, const std::string& msg)
 constexpr uint64_t kMagic = 0x31414c5044464848ull;
 constexpr uint64_t kDead = 0xdeaddeaddeaddeadull;
 constexpr unsigned kKnownFlags =
-    HFD_FP64 | HFD_MIX_SPLIT_BF16 | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR | HFD_MIX_BATCHED_FP32;
+    HFD_FP64 | HFD_MIX_SPLIT_BF16 | HFD_SPLIT_PASSES | HFD_STORE_DTENSOR | HFD_MIX_BATCHED_FP32 |
+    HFD_EQUIDISTANT;
 
 int next_pow2(long long v)
 {
@@ -122,9 +124,14 @@ struct hfd_plan_s {
     int dchunk = 0;
     double* partial = nullptr;  // reduction partials [batch_max][nblk][2 nz]
     int nblk = 0;
+    // equidistant stack: layer sum by FFT along z (path 4)
+    bool eq3d = false;
+    int Lz = 0;                 // padded length along z
+    void* Bc = nullptr;         // [2][batch_max][S][Ly]: split-off column Lx/2 in / out
+    void* twz = nullptr;        // plan precision, length Lz
     // field path: 0 fused y-pass, 1 five-pass generic mixing, 2 five-pass batched
-    // FP32 mixing, 3 five-pass split-BF16 MFMA mixing; default from the flags,
-    // per-batch choice from hfd_autotune
+    // FP32 mixing, 3 five-pass split-BF16 MFMA mixing, 4 equidistant (z FFT);
+    // default from the flags, per-batch choice from hfd_autotune
     int path = 0;
     std::map<int, int> tuned;
 };
@@ -208,7 +215,7 @@ void free_plan_memory(hfd_plan p)
     if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
-                    p->D, p->zidx, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale};
+                    p->D, p->zidx, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
@@ -220,6 +227,7 @@ void free_plan_memory(hfd_plan p)
     p->zidx = nullptr;
     p->zeta_dev = nullptr;
     p->partial = nullptr;
+    p->Bc = p->twz = nullptr;
 }
 
 // twiddle table exp(-2 pi i m / L), m in [0, L), in FP64 (exact octant reduction)
@@ -242,9 +250,22 @@ hfd_status upload_twiddles(hfd_plan p, hipStream_t s)
     HFD_TRY(dev_alloc(&p->twy64, ty.size() * 8, "twiddles"));
     HFD_HIP(hipMemcpyAsync(p->twx64, tx.data(), tx.size() * 8, hipMemcpyHostToDevice, s));
     HFD_HIP(hipMemcpyAsync(p->twy64, ty.data(), ty.size() * 8, hipMemcpyHostToDevice, s));
+    if (p->eq3d) {  // z-transform table in the plan precision (both precisions)
+        auto tz = twiddles(p->Lz);
+        if (p->fp64) {
+            HFD_TRY(dev_alloc(&p->twz, tz.size() * 8, "twiddles"));
+            HFD_HIP(hipMemcpyAsync(p->twz, tz.data(), tz.size() * 8, hipMemcpyHostToDevice, s));
+        } else {
+            std::vector<float> fz(tz.begin(), tz.end());
+            HFD_TRY(dev_alloc(&p->twz, fz.size() * 4, "twiddles"));
+            HFD_HIP(hipMemcpyAsync(p->twz, fz.data(), fz.size() * 4, hipMemcpyHostToDevice, s));
+        }
+        HFD_HIP(hipStreamSynchronize(s));
+    }
     if (p->fp64) {
         p->twx = p->twx64;
         p->twy = p->twy64;
+        HFD_HIP(hipStreamSynchronize(s));
         return HFD_OK;
     }
     std::vector<float> fx(tx.begin(), tx.end()), fy(ty.begin(), ty.end());
@@ -256,74 +277,41 @@ hfd_status upload_twiddles(hfd_plan p, hipStream_t s)
     return HFD_OK;
 }
 
-// Build the Fourier tensor of every stack (FP64 setup, stored in plan precision).
-hfd_status build_tensor(hfd_plan p, hipStream_t s)
+// FP64 2D spectra (x and y transforms of the zero-padded real-space tensor,
+// 6 components each) of the cuboid-pair geometries `geos`, in chunks that fit
+// a 512 MB scratch budget; after each chunk pack(first, count, F) enqueues the
+// packing of spectra F[count][6][M][Ly] (complex, interleaved re/im doubles).
+// Synchronizes the stream at the end.
+template <class Pack>
+hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
 {
+    const int n = (int)geos.size();
     const long long plane = (long long)p->Lx * p->Ly;
     const long long per_pair = 6 * plane * 8;  // FP64 real arrays per pair (same for the spectra)
     const long long budget = 512LL << 20;
-    int CP = (int)std::max(1LL, std::min<long long>(p->P, budget / per_pair));
+    const int CP = (int)std::max(1LL, std::min<long long>(n, budget / per_pair));
     double* W = nullptr;
     void* F = nullptr;
     PairGeoH* pg = nullptr;
-    double* scale = nullptr;
     hfd_status st = HFD_OK;
     do {
         st = dev_alloc(&W, (size_t)CP * per_pair, "tensor setup (real space)");
         if (st) break;
         st = dev_alloc(&F, (size_t)CP * per_pair, "tensor setup (spectra)");
         if (st) break;
-        st = dev_alloc(&pg, sizeof(PairGeoH) * (size_t)p->P, "pair table");
+        st = dev_alloc(&pg, sizeof(PairGeoH) * (size_t)n, "pair table");
         if (st) break;
-        st = dev_alloc(&scale, sizeof(double) * (size_t)p->P, "pair scales");
-        if (st) break;
-        std::vector<PairGeoH> hp((size_t)p->P);
-        std::vector<double> hs((size_t)p->P);
-        for (int g = 0; g < p->G && st == HFD_OK; ++g) {
-            const double* t = &p->thick[(size_t)g * p->nz];
-            const double* z = &p->zbot[(size_t)g * p->nz];
-            int u = 0;
-            for (int i = 0; i < p->nz; ++i)
-                for (int j = i; j < p->nz; ++j, ++u) {
-                    hp[u] = {t[i], t[j], z[i] - z[j], 0.0};
-                    hs[u] = -t[i] / (double)plane;
-                }
-            hipError_t e = hipMemcpyAsync(pg, hp.data(), sizeof(PairGeoH) * p->P, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(scale, hs.data(), sizeof(double) * p->P, hipMemcpyHostToDevice, s);
-            for (int u0 = 0; u0 < p->P && e == hipSuccess; u0 += CP) {
-                const int np = std::min(CP, p->P - u0);
-                e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
-                if (e == hipSuccess)
-                    e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
-                if (e == hipSuccess)
-                    e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
-                if (e == hipSuccess)
-                    e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
-                if (e == hipSuccess) {
-                    char* qdst = (char*)p->Q + (size_t)g * p->q_geom_stride * p->rsz;
-                    e = launch_pack(p->fp64, F, qdst, scale + u0, np, 5, p->M, p->Ly, p->QX, p->QY,
-                                    u0, p->P, s);
-                }
-            }
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
-        }
-        if (st) break;
-        // layer parameters: 1/t and the self-pair trace -t/(Lx Ly)
-        std::vector<double> lp((size_t)p->G * 2 * p->nz);
-        for (int g = 0; g < p->G; ++g)
-            for (int l = 0; l < p->nz; ++l) {
-                const double t = p->thick[(size_t)g * p->nz + l];
-                lp[((size_t)g * 2) * p->nz + l] = 1.0 / t;
-                lp[((size_t)g * 2 + 1) * p->nz + l] = -t / (double)plane;
-            }
-        hipError_t e;
-        if (p->fp64) {
-            e = hipMemcpyAsync(p->lp, lp.data(), lp.size() * 8, hipMemcpyHostToDevice, s);
-        } else {
-            std::vector<float> lf(lp.begin(), lp.end());
-            e = hipMemcpyAsync(p->lp, lf.data(), lf.size() * 4, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipError_t e = hipMemcpyAsync(pg, geos.data(), sizeof(PairGeoH) * n, hipMemcpyHostToDevice, s);
+        for (int u0 = 0; u0 < n && e == hipSuccess; u0 += CP) {
+            const int np = std::min(CP, n - u0);
+            e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
+            if (e == hipSuccess)
+                e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
+            if (e == hipSuccess)
+                e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
+            if (e == hipSuccess)
+                e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
+            if (e == hipSuccess) e = pack(u0, np, (const double*)F);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
@@ -331,9 +319,132 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
     if (W) (void)hipFree(W);
     if (F) (void)hipFree(F);
     if (pg) (void)hipFree(pg);
-    if (scale) (void)hipFree(scale);
-    p->d_valid = false;
     return st;
+}
+
+// Build the Fourier tensor of every stack (FP64 setup, stored in plan precision).
+// Pairs with the same geometry (thicknesses and offset; e.g. every pair at
+// the same layer distance of an equal-thickness stack) are computed once.
+hfd_status build_tensor(hfd_plan p, hipStream_t s)
+{
+    const long long plane = (long long)p->Lx * p->Ly;
+    double* scale = nullptr;
+    hfd_status st = dev_alloc(&scale, sizeof(double) * (size_t)p->P, "pair scales");
+    if (st) return st;
+    std::vector<PairGeoH> ug;
+    std::vector<int> uid((size_t)p->P);
+    std::vector<double> hs((size_t)p->P);
+    for (int g = 0; g < p->G && st == HFD_OK; ++g) {
+        const double* t = &p->thick[(size_t)g * p->nz];
+        const double* z = &p->zbot[(size_t)g * p->nz];
+        ug.clear();
+        std::map<std::tuple<double, double, double>, int> seen;
+        int u = 0;
+        for (int i = 0; i < p->nz; ++i)
+            for (int j = i; j < p->nz; ++j, ++u) {
+                const auto key = std::make_tuple(t[i], t[j], z[i] - z[j]);
+                auto it = seen.find(key);
+                if (it == seen.end()) {
+                    it = seen.emplace(key, (int)ug.size()).first;
+                    ug.push_back({t[i], t[j], z[i] - z[j], 0.0});
+                }
+                uid[u] = it->second;
+                hs[u] = -t[i] / (double)plane;
+            }
+        if (hipMemcpyAsync(scale, hs.data(), sizeof(double) * p->P, hipMemcpyHostToDevice, s) != hipSuccess) {
+            st = fail(HFD_EHIP, "tensor setup: scale upload failed");
+            break;
+        }
+        char* qdst = (char*)p->Q + (size_t)g * p->q_geom_stride * p->rsz;
+        const size_t fstride = (size_t)2 * 6 * p->M * p->Ly;  // doubles per geometry
+        st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
+            for (int pu = 0; pu < p->P; ++pu) {
+                const int k = uid[pu];
+                if (k < u0 || k >= u0 + np) continue;
+                hipError_t e = launch_pack(p->fp64, F + (size_t)(k - u0) * fstride, qdst, scale + pu, 1, 5,
+                                           p->M, p->Ly, p->QX, p->QY, pu, p->P, s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        });
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(scale);
+    if (st) return st;
+    // layer parameters: 1/t and the self-pair trace -t/(Lx Ly)
+    std::vector<double> lp((size_t)p->G * 2 * p->nz);
+    for (int g = 0; g < p->G; ++g)
+        for (int l = 0; l < p->nz; ++l) {
+            const double t = p->thick[(size_t)g * p->nz + l];
+            lp[((size_t)g * 2) * p->nz + l] = 1.0 / t;
+            lp[((size_t)g * 2 + 1) * p->nz + l] = -t / (double)plane;
+        }
+    hipError_t e;
+    if (p->fp64) {
+        e = hipMemcpyAsync(p->lp, lp.data(), lp.size() * 8, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    } else {
+        std::vector<float> lf(lp.begin(), lp.end());
+        e = hipMemcpyAsync(p->lp, lf.data(), lf.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) return fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
+    p->d_valid = false;
+    return HFD_OK;
+}
+
+// Equidistant stack: the 2D spectra of N(d) for the 2nz - 1 layer offsets d
+// (FP64, all 6 components on the quadrant), then the transform along z to the
+// real 3-D Fourier tensor [kx][kz][6][ky] (eq. FFT_3D), scaled by -1/(Lx Ly Lz).
+hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
+{
+    const long long plane = (long long)p->Lx * p->Ly;
+    const int nd = 2 * p->nz - 1;
+    const double t = p->thick[0];
+    const double pitch = p->nz > 1 ? p->zbot[1] - p->zbot[0] : t;
+    std::vector<PairGeoH> geos((size_t)nd);
+    for (int k = 0; k < nd; ++k) geos[k] = {t, t, (double)(k - (p->nz - 1)) * pitch, 0.0};
+    std::vector<double> hs((size_t)nd, -1.0 / (double)plane);
+    double* scale = nullptr;
+    double* Q2 = nullptr;
+    const size_t per = (size_t)6 * p->QX * p->QY;
+    hfd_status st = dev_alloc(&scale, sizeof(double) * nd, "offset scales");
+    if (st == HFD_OK) st = dev_alloc(&Q2, sizeof(double) * per * nd, "per-offset spectra");
+    if (st == HFD_OK &&
+        hipMemcpyAsync(scale, hs.data(), sizeof(double) * nd, hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(HFD_EHIP, "tensor setup: scale upload failed");
+    if (st == HFD_OK)
+        st = tensor_spectra(p, geos, s, [&](int u0, int np, const double* F) -> hipError_t {
+            return launch_pack(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->Ly, p->QX,
+                               p->QY, 0, np, s);
+        });
+    if (st == HFD_OK) {
+        hipError_t e = launch_zdft3(p->fp64, Q2, p->Q, p->nz, p->Lz, p->QX, p->QY, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(s);
+    if (scale) (void)hipFree(scale);
+    if (Q2) (void)hipFree(Q2);
+    return st;
+}
+
+// Equal thicknesses and a uniform pitch (relative tolerance 1e-12), one stack.
+hfd_status check_equidistant(int nz, int G, const std::vector<double>& t, const std::vector<double>& z)
+{
+    if (G != 1) return fail(HFD_EINVAL, "HFD_EQUIDISTANT needs n_geom = 1");
+    for (int l = 1; l < nz; ++l)
+        if (std::fabs(t[l] - t[0]) > 1e-12 * t[0])
+            return fail(HFD_EINVAL, "HFD_EQUIDISTANT needs equal thicknesses");
+    if (nz > 2) {
+        const double p0 = z[1] - z[0];
+        for (int l = 2; l < nz; ++l) {
+            const double pl = z[l] - z[l - 1];
+            if (std::fabs(pl - p0) > 1e-12 * std::max(std::fabs(z[l]), p0))
+                return fail(HFD_EINVAL, "HFD_EQUIDISTANT needs a uniform pitch z_bottom[l+1] - z_bottom[l]");
+        }
+    }
+    return HFD_OK;
 }
 
 
@@ -506,7 +617,8 @@ const char* path_name(int path)
     case 0: return "fused";
     case 1: return "five_pass";
     case 2: return "five_pass_batched_fp32";
-    default: return "five_pass_bf16_mfma";
+    case 3: return "five_pass_bf16_mfma";
+    default: return "equidistant_z_fft";
     }
 }
 
@@ -541,7 +653,13 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
         if (on()) HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
         mark();
         if (on()) {
-            if (path == 2 || path == 3) {
+            if (path == 4) {
+                // equidistant: unpack the packed column, z pass, repack
+                char* bc = (char*)p->Bc;
+                char* hbc = bc + (size_t)p->batch_max * 3 * p->nz * p->Ly * p->csz;
+                HFD_HIP(launch_eq3d_mix(p->fp64, p->Lz, p->Mh, bc, p->Hh, hbc, p->nz, p->M, p->Ly,
+                                        batch, p->Q, p->QY, p->twz, s));
+            } else if (path == 2 || path == 3) {
                 // packed column by the generic kernel, the rest batched
                 HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
                                            p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1,
@@ -572,7 +690,8 @@ std::string stage_names(int path)
     case 0: return "xfwd;ymix_fused;xinv";
     case 1: return "xfwd;yfwd;mix;yinv;xinv";
     case 2: return "xfwd;yfwd;mix_batched_fp32;yinv;xinv";
-    default: return "xfwd;yfwd;mix_bf16_mfma;yinv;xinv";
+    case 3: return "xfwd;yfwd;mix_bf16_mfma;yinv;xinv";
+    default: return "xfwd;yfwd;zpass;yinv;xinv";
     }
 }
 
@@ -601,6 +720,8 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 / HFD_MIX_BATCHED_FP32 require the FP32 field path");
     if ((flags & HFD_MIX_SPLIT_BF16) && (flags & HFD_MIX_BATCHED_FP32))
         return fail(HFD_EINVAL, "HFD_MIX_SPLIT_BF16 and HFD_MIX_BATCHED_FP32 are exclusive");
+    if ((flags & HFD_EQUIDISTANT) && (flags & ~(HFD_EQUIDISTANT | HFD_FP64)))
+        return fail(HFD_EINVAL, "HFD_EQUIDISTANT combines with HFD_FP64 only");
 
     hfd_plan p = new (std::nothrow) hfd_plan_s();
     if (!p) return fail(HFD_ENOMEM, "host allocation of the plan failed");
@@ -619,13 +740,21 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     p->P = nz * (nz + 1) / 2;
     hfd_status st = validate_geometry(nz, n_geom, thickness, z_bottom, p->thick, p->zbot);
     if (st) { delete p; return st; }
-    p->fused = !(flags & HFD_SPLIT_PASSES) && !p->bf16 && !p->batched32 &&
+    p->eq3d = flags & HFD_EQUIDISTANT;
+    if (p->eq3d) {
+        st = check_equidistant(nz, n_geom, p->thick, p->zbot);
+        if (st) { delete p; return st; }
+        p->Lz = std::max(2, next_pow2(2LL * nz));
+    }
+    p->fused = !(flags & HFD_SPLIT_PASSES) && !p->bf16 && !p->batched32 && !p->eq3d &&
                fused_supported(p->fp64, p->Ly, nz, nullptr);
-    p->path = p->fused ? 0 : (p->bf16 ? 3 : (p->batched32 ? 2 : 1));
+    p->path = p->eq3d ? 4 : (p->fused ? 0 : (p->bf16 ? 3 : (p->batched32 ? 2 : 1)));
 
     // sizes (overflow checked)
     const long long S = 3LL * nz;
-    const long long q_per_geom = mul_ll(mul_ll((long long)p->P * 5, p->QX), p->QY);
+    const long long q_per_geom = p->eq3d ? mul_ll(mul_ll((long long)(p->Lz / 2 + 1) * 6, p->QX), p->QY)
+                                         : mul_ll(mul_ll((long long)p->P * 5, p->QX), p->QY);
+    const long long bc = p->eq3d ? mul_ll(mul_ll(2LL * batch_max, S), (long long)p->Ly * (long long)p->csz) : 0;
     const long long q_elems = mul_ll(q_per_geom, n_geom);
     const long long x1 = mul_ll(mul_ll(mul_ll((long long)batch_max, S), p->M), (long long)ny * (long long)p->csz);
     const long long mh = mul_ll(mul_ll(mul_ll((long long)batch_max, S), p->M), (long long)p->Ly * (long long)p->csz);
@@ -638,7 +767,7 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     if (hipGetDevice(&p->dev) != hipSuccess) { delete p; return fail(HFD_EHIP, "hipGetDevice failed"); }
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) == hipSuccess) {
-        const long double need = (long double)q_elems * p->rsz + (long double)x1 + 2.0L * mh;
+        const long double need = (long double)q_elems * p->rsz + (long double)x1 + 2.0L * mh + (long double)bc;
         if (need > (long double)freeb) {
             delete p;
             return fail(HFD_ENOMEM, "plan needs " + std::to_string((double)need) + " bytes of device memory, " +
@@ -656,8 +785,16 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         if (st) break;
         st = dev_alloc(&p->Hh, p->mh_bytes, "spectrum workspace");
         if (st) break;
+        if (p->eq3d) {
+            st = dev_alloc(&p->Bc, (size_t)bc, "split-column workspace");
+            if (st) break;
+        }
         st = upload_twiddles(p, s);
         if (st) break;
+        if (p->eq3d) {
+            st = build_tensor3d(p, s);
+            break;
+        }
         st = build_tensor(p, s);
         if (st) break;
         st = setup_derivatives(p, s);
@@ -686,11 +823,13 @@ hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* 
     HFD_TRY(check_plan(p));
     std::vector<double> t, z;
     HFD_TRY(validate_geometry(p->nz, p->G, thickness, z_bottom, t, z));
+    if (p->eq3d) HFD_TRY(check_equidistant(p->nz, p->G, t, z));
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
     p->thick = t;
     p->zbot = z;
     hipStream_t s = (hipStream_t)stream;
+    if (p->eq3d) return build_tensor3d(p, s);
     HFD_TRY(build_tensor(p, s));
     HFD_TRY(setup_derivatives(p, s));
     if (p->flags & HFD_STORE_DTENSOR) {
@@ -715,6 +854,8 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
 {
     HFD_TRY(check_plan(p));
     if (!grad_m && !grad_thickness) return fail(HFD_EINVAL, "grad_m and grad_thickness are both NULL");
+    if (p->eq3d && grad_thickness)
+        return fail(HFD_ENOTSUP, "thickness gradients need the non-equidistant plan (no HFD_EQUIDISTANT)");
     if (grad_m) HFD_TRY(check_field_args(p, grad_h, grad_m, batch, "grad_h", "grad_m"));
     if (grad_thickness) {
         HFD_TRY(check_field_args(p, m, grad_h, batch, "m", "grad_h"));
@@ -806,11 +947,15 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     // candidates: every compiled path valid for this plan; split-BF16 only when
     // the plan was created with it (it changes the rounding of the mixing)
     std::vector<int> cand;
-    if (!(p->flags & HFD_SPLIT_PASSES) && fused_supported(p->fp64, p->Ly, p->nz, nullptr)) cand.push_back(0);
-    cand.push_back(1);
+    if (p->eq3d) cand.push_back(4);
+    else {
+        if (!(p->flags & HFD_SPLIT_PASSES) && fused_supported(p->fp64, p->Ly, p->nz, nullptr))
+            cand.push_back(0);
+        cand.push_back(1);
+    }
     // the batched kernels apply each frequency matrix to 16 states at a time;
     // below that they are not worth timing
-    if (!p->fp64 && batch >= 16 && mix_batched_supported(p->nz, batch, p->G)) {
+    if (!p->eq3d && !p->fp64 && batch >= 16 && mix_batched_supported(p->nz, batch, p->G)) {
         cand.push_back(2);
         if (p->bf16) cand.push_back(3);
     }
@@ -867,6 +1012,9 @@ hfd_status hfd_get_info(hfd_plan p, hfd_info* info)
     info->fused = p->fused; info->fp64 = p->fp64; info->mix_bf16 = p->bf16;
     info->tensor_bytes = p->q_geom_stride * (long long)p->G * (long long)p->rsz;
     info->work_bytes = (long long)(p->x1_bytes + 2 * p->mh_bytes);
+    if (p->eq3d) info->work_bytes += 2LL * p->batch_max * 3 * p->nz * p->Ly * (long long)p->csz;
+    info->equidistant = p->eq3d;
+    info->Lz = p->Lz;
     return HFD_OK;
 }
 

@@ -42,6 +42,14 @@ hipError_t launch_mix_batched(bool mfma, const void* Mh, void* Hh, int nz, int M
                               const void* Q, long long q_geom_stride, int QY, const void* lp, int bpg,
                               int adjoint, hipStream_t s);
 
+// equidistant stacks: 3-D Fourier tensor from the per-offset 2D spectra, and
+// the z pass on the five-pass spectra (packed column unpacked into Bc and
+// repacked; Bc, HBc: [B][3nz][LY])
+hipError_t launch_zdft3(bool out_fp64, const double* Q2, void* T3, int nz, int LZ, int QX, int QY,
+                        hipStream_t s);
+hipError_t launch_eq3d_mix(bool fp64, int LZ, void* Mh, void* Bc, void* Hh, void* HBc, int nz, int M,
+                           int LY, int B, const void* T3, int QY, const void* twz, hipStream_t s);
+
 // thickness-gradient reduction over the spectra (states b0 .. b0+nb-1)
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
                         int nb, const void* Q, long long qgs, const void* D, long long dgs,

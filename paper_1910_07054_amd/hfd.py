@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhfd.so")
 HFD_OK, HFD_EINVAL, HFD_ENOMEM, HFD_EHIP, HFD_EBATCH, HFD_EHANDLE, HFD_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 HFD_FP32, HFD_FP64, HFD_MIX_SPLIT_BF16, HFD_SPLIT_PASSES, HFD_STORE_DTENSOR = 0, 1, 2, 4, 8
 HFD_MIX_BATCHED_FP32 = 16
+HFD_EQUIDISTANT = 32
 
 STATUS_NAMES = {0: "HFD_OK", -1: "HFD_EINVAL", -2: "HFD_ENOMEM", -3: "HFD_EHIP", -4: "HFD_EBATCH",
                 -5: "HFD_EHANDLE", -6: "HFD_ENOTSUP"}
@@ -42,7 +43,8 @@ class Info(ctypes.Structure):
                 ("n_geom", ctypes.c_int), ("batch_max", ctypes.c_int), ("Lx", ctypes.c_int),
                 ("Ly", ctypes.c_int), ("fused", ctypes.c_int), ("fp64", ctypes.c_int),
                 ("mix_bf16", ctypes.c_int), ("tensor_bytes", ctypes.c_longlong),
-                ("work_bytes", ctypes.c_longlong)]
+                ("work_bytes", ctypes.c_longlong), ("equidistant", ctypes.c_int),
+                ("Lz", ctypes.c_int)]
 
 
 _lib = None
@@ -200,10 +202,12 @@ class Plan:
 
     # -- inspection ----------------------------------------------------------
     def export_fourier_tensor(self, geom: int = 0) -> np.ndarray:
+        """[Lx/2+1][P][5][Ly/2+1]; equidistant plans: [Lx/2+1][Lz/2+1][6][Ly/2+1]."""
         inf = self.info()
         P = self.nz * (self.nz + 1) // 2
         QX, QY = inf.Lx // 2 + 1, inf.Ly // 2 + 1
-        out = np.empty((QX, P, 5, QY), dtype=np.float64 if self.fp64 else np.float32)
+        shape = (QX, inf.Lz // 2 + 1, 6, QY) if inf.equidistant else (QX, P, 5, QY)
+        out = np.empty(shape, dtype=np.float64 if self.fp64 else np.float32)
         _check(load().hfd_export_fourier_tensor(self.handle, int(geom), out.ctypes.data, out.nbytes))
         return out
 

@@ -69,6 +69,12 @@ def _setup(**kw):
     (dict(n_geom=2, batch_max=1, thickness=np.ones(4)), "batch_max"),
     (dict(flags=1 << 10), "flag"),
     (dict(flags=hfd.HFD_FP64 | hfd.HFD_MIX_SPLIT_BF16), "BF16"),
+    (dict(flags=hfd.HFD_EQUIDISTANT | hfd.HFD_SPLIT_PASSES), "EQUIDISTANT"),
+    (dict(flags=hfd.HFD_EQUIDISTANT | hfd.HFD_MIX_SPLIT_BF16), "EQUIDISTANT"),
+    (dict(flags=hfd.HFD_EQUIDISTANT, thickness=np.array([1.0, 1.2])), "equal thicknesses"),
+    (dict(flags=hfd.HFD_EQUIDISTANT, nz=3, thickness=np.ones(3),
+          z_bottom=np.array([0.0, 1.0, 2.5])), "uniform pitch"),
+    (dict(flags=hfd.HFD_EQUIDISTANT, n_geom=2, batch_max=2, thickness=np.ones(4)), "n_geom"),
 ])
 def test_setup_rejects_invalid_arguments(kw, frag):
     st, msg = _setup(**kw)

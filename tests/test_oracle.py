@@ -420,6 +420,43 @@ def test_thickness_gradient_uniform_mode_equals_full_mode():
 
 
 # ---------------------------------------------------------------------------
+# Equidistant case (eq. FFT_3D): the 3-D transform reproduces the direct sum
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,nz,t,pitch", [(7, 5, 4, 0.8, 1.3), (6, 9, 3, 1.1, 1.1), (5, 4, 1, 0.6, 0.6)])
+def test_fft3_field_matches_bruteforce(nx, ny, nz, t, pitch):
+    rng = np.random.default_rng(40 + nz)
+    m = rng.standard_normal((3, nz, ny, nx))
+    zb = np.arange(nz) * pitch
+    h3 = oracle.fft3_field(nx, ny, 2.0, 1.5, t, pitch, m)
+    hb = oracle.field(nx, ny, 2.0, 1.5, zb, np.full(nz, t), m)
+    assert np.abs(h3 - hb).max() <= 1e-13 * np.abs(hb).max()
+
+
+def test_fourier_tensor3_is_real_by_parity():
+    """xx, yy, zz, xy even in Z; xz, yz odd in Z and odd in one lateral
+    coordinate: every component of the 3-D transform is real."""
+    T = oracle.fourier_tensor3(6, 5, 2.0, 1.5, 5, 0.9, 1.4)
+    assert np.abs(T.imag).max() <= 1e-13 * np.abs(T.real).max()
+    # odd components change sign with kz -> -kz
+    Lz = T.shape[1]
+    kz = np.arange(1, Lz // 2)
+    for c, sign in ((0, 1), (1, 1), (2, 1), (3, 1), (4, -1), (5, -1)):
+        np.testing.assert_allclose(T[c, Lz - kz].real, sign * T[c, kz].real, atol=1e-13 * np.abs(T).max())
+
+
+def test_hybrid_equals_fft3_on_an_equidistant_stack():
+    """The explicit layer sum (eq. FFT_v2) and the 3-D transform (eq. FFT_3D)
+    give the same field when the layers are equidistant."""
+    rng = np.random.default_rng(41)
+    nx, ny, nz, t, pitch = 6, 7, 5, 0.7, 1.0
+    m = rng.standard_normal((3, nz, ny, nx))
+    zb = np.arange(nz) * pitch
+    h2 = oracle.fft_field(nx, ny, 2.5, 2.5, zb, np.full(nz, t), m)
+    h3 = oracle.fft3_field(nx, ny, 2.5, 2.5, t, pitch, m)
+    assert np.abs(h2 - h3).max() <= 1e-13 * np.abs(h2).max()
+
+
+# ---------------------------------------------------------------------------
 # The paper's worked example (Sec. 4): MRAM SAFM thickness optimum 3.44 nm
 # ---------------------------------------------------------------------------
 def _mram_mean_hz(t_mid):
