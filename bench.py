@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--compare", action="store_true",
                     help="also time every mixing path (and 64 single-state calls) on the workload, "
                          "each with its error against the stored oracle values")
+    ap.add_argument("--nz-sweep", action="store_true",
+                    help="also time the explicit layer sum and the equidistant z-FFT path on "
+                         "256x256 x nz equal-thickness stacks, nz = 1 .. 64 (Sec. 3.2 scaling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -191,6 +194,50 @@ def compare_paths(wl, m, steps, warmup, stream):
     return res
 
 
+def nz_sweep(steps, warmup, stream, nzs=(1, 2, 4, 8, 16, 32, 64)):
+    """Field evaluation time of the explicit layer sum (fastest path after
+    autotuning) and of the equidistant z-FFT path on the same 256 x 256 x nz
+    stack of equal 1 nm layers (2.5 nm cells, no gaps, alternating +-z
+    magnetization with a small tilt), with the least-squares fits of Sec. 3.2:
+    a nz^2 + b nz + c and a nz log nz + b."""
+    import torch
+    from paper_1910_07054_amd import hfd
+    from paper_1910_07054_amd import workloads as W
+    rows = []
+    for nz in nzs:
+        rng = np.random.default_rng(1100 + nz)
+        t = np.ones(nz)
+        zb = np.arange(nz, dtype=np.float64)
+        m = torch.from_numpy(W.tilted_alternating(rng, nz, 256, 256)[None].astype(np.float32)).cuda()
+        row = {"nz": nz}
+        outs = {}
+        for name, fl in (("layer_sum", hfd.HFD_FP32), ("equidistant", hfd.HFD_EQUIDISTANT)):
+            t0 = time.perf_counter()
+            plan = hfd.Plan(256, 256, 2.5, 2.5, t, zb, batch_max=1, flags=fl)
+            setup = time.perf_counter() - t0
+            rep = plan.autotune(1)
+            h = torch.empty_like(m)
+            ms = replay_ms(lambda: plan.field(m, out=h, stream=stream), steps, warmup, stream)
+            outs[name] = h.double()
+            row[name + "_ms"] = ms
+            row[name + "_setup_s"] = setup
+            row[name + "_path"] = rep.split("-> ")[-1]
+            plan.destroy()
+        d = (outs["layer_sum"] - outs["equidistant"]).abs().max().item()
+        row["max_diff_rel"] = d / outs["layer_sum"].norm(dim=1).max().item()
+        print(f"nz_sweep nz={nz}: " + json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+        del m, outs
+        torch.cuda.empty_cache()
+    x = np.array([r["nz"] for r in rows], dtype=np.float64)
+    y1 = np.array([r["layer_sum_ms"] for r in rows])
+    y2 = np.array([r["equidistant_ms"] for r in rows])
+    a1 = np.linalg.lstsq(np.stack([x * x, x, np.ones_like(x)], 1), y1, rcond=None)[0]
+    a2 = np.linalg.lstsq(np.stack([x * np.log(x), np.ones_like(x)], 1), y2, rcond=None)[0]
+    return {"rows": rows, "fit_layer_sum_ms": {"a_nz2": a1[0], "b_nz": a1[1], "c": a1[2]},
+            "fit_equidistant_ms": {"a_nzlognz": a2[0], "b": a2[1]}}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -310,6 +357,8 @@ def main():
     }
     if args.compare:
         out["path_comparison"] = compare_paths(wl, m, args.steps, args.warmup, stream)
+    if args.nz_sweep:
+        out["nz_sweep"] = nz_sweep(max(args.steps // 4, 20), args.warmup, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     plan.destroy()

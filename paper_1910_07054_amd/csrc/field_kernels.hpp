@@ -653,17 +653,27 @@ __global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yinv(const cpx<R>* 
         });
 }
 
-// Generic z-mixing on full spectra, one thread per (state, kx column, ky).
-template <typename R>
-__global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ Mh,
-                                                     cpx<R>* __restrict__ Hh, int nz, int M, int LY,
-                                                     const R* __restrict__ Q,
-                                                     long long q_geom_stride, int QX, int QY,
-                                                     const R* __restrict__ lp, int bpg, int adjoint,
-                                                     int kx0)
+// Five-pass z-mixing on full spectra (any nz).  Lanes 2t' and 2t'+1 of a wave
+// take the ky points t and LY - t (t = 0: ky = 0 and LY/2), which share one
+// quadrant tensor entry; the waves of a block take consecutive groups of IB
+// target layers of the same points, each lane summing over all source layers
+// with its IB targets' accumulators in registers.  Grid: (ceil((LY/2) / 32),
+// nkx columns from kx0, B), block 64 ceil(nz / IB) <= 512 threads.
+// Column 0 carries kx = 0 and Lx/2 packed as A + iB: lane p = 0 mixes A(t)
+// with the kx = 0 row and lane p = 1 B(t) with the kx = Lx/2 row, and the pair
+// repacks through a lane shuffle; the self-mirrored points t = 0 (ky = 0 and
+// LY/2) mix both parts on one lane.
+template <typename R, int IB>
+__global__ __launch_bounds__(512) void k_mix_pairs(const cpx<R>* __restrict__ Mh,
+                                                    cpx<R>* __restrict__ Hh, int nz, int M, int LY,
+                                                    const R* __restrict__ Q,
+                                                    long long q_geom_stride, int QY,
+                                                    const R* __restrict__ lp, int bpg, int adjoint,
+                                                    int kx0)
 {
-    const int ky = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ky >= LY) return;
+    const int lane = threadIdx.x & 63, i0 = (threadIdx.x >> 6) * IB;
+    const int t = blockIdx.x * 32 + (lane >> 1), p = lane & 1;
+    if (t >= LY / 2) return;  // no block-level synchronization below
     const int kx = kx0 + blockIdx.y, b = blockIdx.z;
     const int S = 3 * nz, geom = b / bpg;
     const long long sst = (long long)M * LY;
@@ -671,55 +681,85 @@ __global__ __launch_bounds__(256) void k_mix_generic(const cpx<R>* __restrict__ 
     cpx<R>* hb = Hh + ((long long)b * S * M + kx) * LY;
     const R* lpg = lp + (long long)geom * 2 * nz;
     const R* Qg = Q + (long long)geom * q_geom_stride;
-    const long long cs = QY;                          // component stride
     const long long colstride = (long long)nz * (nz + 1) / 2 * 5 * QY;
-    const int half = LY / 2;
-    const int kq = ky <= half ? ky : LY - ky;        // quadrant column
-    const R sg = ky <= half ? R(1) : R(-1);          // sign of the ky-odd components
-    const int kyn = (LY - ky) & (LY - 1);            // -ky
-    for (int i = 0; i < nz; ++i) {
-        cpx<R> acc[2][3];
-        for (int p = 0; p < 2; ++p)
-            for (int c = 0; c < 3; ++c) acc[p][c] = {R(0), R(0)};
+    const R* dg = lpg + nz;
+
+    // H[IB][3] += S^{ij} v_j over all sources j; row: tensor row (kx) base,
+    // kq: quadrant column, sg: sign of the ky-odd components
+    auto mix = [&](cpx<R> (&H)[IB][3], const R* row, int kq, R sg, auto in) {
+        for (int k = 0; k < IB; ++k)
+            for (int c = 0; c < 3; ++c) H[k][c] = {R(0), R(0)};
         for (int j = 0; j < nz; ++j) {
-            const int a = i < j ? i : j, bq = i < j ? j : i;
-            const int u = a * nz - a * (a - 1) / 2 + (bq - a);
-            const R simag = i <= j ? R(1) : R(-1);     // conj for the transposed pair
             const R sc = adjoint ? lpg[j] : R(1);
-            const R dgi = (i == j) ? lpg[nz + i] : R(0);
-            const int npts = (kx == 0) ? 2 : 1;
-            for (int p = 0; p < npts; ++p) {
-                const int row = (kx == 0) ? (p == 0 ? 0 : M) : kx;
-                const R* q = Qg + (long long)row * colstride + (long long)u * 5 * QY + kq;
-                const R xx = q[0], yy = q[cs], xy = q[2 * cs] * sg, xz = q[3 * cs] * simag,
-                        yz = q[4 * cs] * sg * simag;
-                const R zz = -(xx + yy) + dgi;
-                cpx<R> v[3];
-                for (int c = 0; c < 3; ++c) {
-                    const cpx<R> z1 = mb[(c * nz + j) * sst + ky];
-                    if (kx == 0) {
-                        const cpx<R> z2 = mb[(c * nz + j) * sst + kyn];
-                        v[c] = (p == 0) ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
-                                        : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
-                    } else {
-                        v[c] = z1;
-                    }
-                    v[c] = cscale(v[c], sc);
+            const cpx<R> X = cscale(in(0, j), sc), Y = cscale(in(1, j), sc), Z = cscale(in(2, j), sc);
+#pragma unroll
+            for (int k = 0; k < IB; ++k) {
+                const int i = i0 + k;
+                if (i < nz) {
+                    const int a = i < j ? i : j, bq = i < j ? j : i;
+                    const R* q = row + (long long)(a * nz - a * (a - 1) / 2 + (bq - a)) * 5 * QY + kq;
+                    const R simag = i <= j ? R(1) : R(-1);  // conj for the transposed pair
+                    const R xx = q[0], yy = q[QY], xy = sg * q[2 * QY], xz = simag * q[3 * QY],
+                            yz = sg * simag * q[4 * QY];
+                    const R zz = -(xx + yy) + (i == j ? dg[i] : R(0));
+                    block_apply(H[k][0], H[k][1], H[k][2], X, Y, Z, xx, yy, zz, xy, xz, yz);
                 }
-                block_apply(acc[p][0], acc[p][1], acc[p][2], v[0], v[1], v[2], xx, yy, zz, xy, xz, yz);
             }
         }
-        const R post = adjoint ? R(1) : lpg[i];
-        for (int c = 0; c < 3; ++c) {
-            cpx<R> w;
-            if (kx == 0) {
-                const cpx<R> A = acc[0][c], B = acc[1][c];
-                w = {A.x - B.y, A.y + B.x};
-            } else {
-                w = acc[0][c];
+    };
+    auto store = [&](const cpx<R> (&H)[IB][3], int ky) {
+#pragma unroll
+        for (int k = 0; k < IB; ++k) {
+            const int i = i0 + k;
+            if (i < nz) {
+                const R post = adjoint ? R(1) : lpg[i];
+                for (int c = 0; c < 3; ++c) hb[(c * nz + i) * sst + ky] = cscale(H[k][c], post);
             }
-            hb[(c * nz + i) * sst + ky] = cscale(w, post);
         }
+    };
+    cpx<R> H[IB][3];
+    if (kx != 0) {
+        const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);
+        const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);
+        const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
+        mix(H, Qg + kx * colstride, kq, sg, [&](int c, int j) { return mb[(c * nz + j) * sst + ky]; });
+        store(H, ky);
+    } else if (t != 0) {
+        // A(t) = (Z(t) + conj Z(-t)) / 2 on lane 0, B(t) = (Z(t) - conj Z(-t)) / (2i) on lane 1
+        const int k1 = t, k2 = LY - t;
+        mix(H, Qg + (p == 0 ? 0 : M) * colstride, t, R(1), [&](int c, int j) {
+            const cpx<R> z1 = mb[(c * nz + j) * sst + k1], z2 = mb[(c * nz + j) * sst + k2];
+            return p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
+                          : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
+        });
+        // W(t) = HA + i HB on lane 0, W(-t) = conj(HA) + i conj(HB) on lane 1
+#pragma unroll
+        for (int k = 0; k < IB; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const cpx<R> o = {__shfl_xor(H[k][c].x, 1), __shfl_xor(H[k][c].y, 1)};
+                const cpx<R> A = p == 0 ? H[k][c] : o, Bv = p == 0 ? o : H[k][c];
+                H[k][c] = p == 0 ? cpx<R>{A.x - Bv.y, A.y + Bv.x} : cpx<R>{A.x + Bv.y, Bv.x - A.y};
+            }
+        store(H, p == 0 ? k1 : k2);
+    } else {
+        // ky = 0 (lane 0) or LY/2 (lane 1), each its own mirror: A = Re Z, B = Im Z;
+        // the point receives A' first and then A' + i B'
+        const int kp = p == 0 ? 0 : LY / 2;
+        mix(H, Qg, kp, R(1), [&](int c, int j) { return cpx<R>{mb[(c * nz + j) * sst + kp].x, R(0)}; });
+        cpx<R> keep[IB][3];
+#pragma unroll
+        for (int k = 0; k < IB; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) keep[k][c] = H[k][c];
+        mix(H, Qg + M * colstride, kp, R(1),
+            [&](int c, int j) { return cpx<R>{mb[(c * nz + j) * sst + kp].y, R(0)}; });
+#pragma unroll
+        for (int k = 0; k < IB; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                H[k][c] = {keep[k][c].x - H[k][c].y, keep[k][c].y + H[k][c].x};
+        store(H, kp);
     }
 }
 

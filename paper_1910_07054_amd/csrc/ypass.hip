@@ -1,4 +1,4 @@
-// Instances of the y-pass column kernels and of the generic z-mixing kernel.
+// Instances of the y-pass column kernels and of the five-pass z-mixing kernel.
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -61,15 +61,19 @@ hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M
                               const void* Q, long long qgs, int QX, int QY, const void* lp,
                               int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
 {
+    (void)QX;
     if (nkx <= 0) return hipSuccess;
-    dim3 grid((LY + 255) / 256, nkx, B);
+    constexpr int IB = 8;
+    const int ngrp = (nz + IB - 1) / IB;
+    if (ngrp > 16) return hipErrorInvalidValue;
+    dim3 grid((LY / 2 + 31) / 32, nkx, B);
     if (fp64)
-        hipLaunchKernelGGL(k_mix_generic<double>, grid, dim3(256), 0, s, (const cpx<double>*)Mh,
-                           (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs, QX, QY,
-                           (const double*)lp, bpg, adjoint, kx0);
+        hipLaunchKernelGGL((k_mix_pairs<double, IB>), grid, dim3(64 * ngrp), 0, s,
+                           (const cpx<double>*)Mh, (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs,
+                           QY, (const double*)lp, bpg, adjoint, kx0);
     else
-        hipLaunchKernelGGL(k_mix_generic<float>, grid, dim3(256), 0, s, (const cpx<float>*)Mh,
-                           (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QX, QY,
+        hipLaunchKernelGGL((k_mix_pairs<float, IB>), grid, dim3(64 * ngrp), 0, s,
+                           (const cpx<float>*)Mh, (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QY,
                            (const float*)lp, bpg, adjoint, kx0);
     return hipGetLastError();
 }
