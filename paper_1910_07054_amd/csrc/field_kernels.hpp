@@ -655,26 +655,37 @@ __global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yinv(const cpx<R>* 
 
 // Five-pass z-mixing on full spectra (any nz).  Lanes 2t' and 2t'+1 of a wave
 // take the ky points t and LY - t (t = 0: ky = 0 and LY/2), which share one
-// quadrant tensor entry; the waves of a block take consecutive groups of IB
-// target layers of the same points, each lane summing over all source layers
-// with its IB targets' accumulators in registers.  Grid: (ceil((LY/2) / 32),
-// nkx columns from kx0, B), block 64 ceil(nz / IB) <= 512 threads.
+// quadrant tensor entry; a block (one wave) takes one group of IB target
+// layers of 32 ky pairs, each lane summing over all source layers with its IB
+// targets' accumulators in registers.  One-dimensional grid, block 64.  Tiles
+// (32 ky pairs of one kx column of one state) are numbered ky tile fastest;
+// block L runs target group (L / 8) % ngrp of tile 8 ((L / 8) / ngrp) + L % 8,
+// so the ngrp blocks of one tile are 8 apart and land on the same XCD (blocks
+// are dispatched to the 8 XCDs in turn): they share the tile's spectra and
+// tensor entries in that XCD's L2.
 // Column 0 carries kx = 0 and Lx/2 packed as A + iB: lane p = 0 mixes A(t)
 // with the kx = 0 row and lane p = 1 B(t) with the kx = Lx/2 row, and the pair
 // repacks through a lane shuffle; the self-mirrored points t = 0 (ky = 0 and
 // LY/2) mix both parts on one lane.
 template <typename R, int IB>
-__global__ __launch_bounds__(512) void k_mix_pairs(const cpx<R>* __restrict__ Mh,
+__global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ Mh,
                                                     cpx<R>* __restrict__ Hh, int nz, int M, int LY,
                                                     const R* __restrict__ Q,
                                                     long long q_geom_stride, int QY,
                                                     const R* __restrict__ lp, int bpg, int adjoint,
-                                                    int kx0)
+                                                    int kx0, int nkx, int B)
 {
-    const int lane = threadIdx.x & 63, i0 = (threadIdx.x >> 6) * IB;
-    const int t = blockIdx.x * 32 + (lane >> 1), p = lane & 1;
+    const int ngrp = (nz + IB - 1) / IB;
+    const int nkyb = (LY / 2 + 31) / 32;
+    const long long L = blockIdx.x;
+    const long long r = L >> 3;
+    const long long tile = (r / ngrp) * 8 + (L & 7);
+    if (tile >= (long long)nkyb * nkx * B) return;  // padding of the last tiles
+    const int kyb = (int)(tile % nkyb);
+    const int kx = kx0 + (int)((tile / nkyb) % nkx), b = (int)(tile / ((long long)nkyb * nkx));
+    const int lane = threadIdx.x & 63, i0 = (int)(r % ngrp) * IB;
+    const int t = kyb * 32 + (lane >> 1), p = lane & 1;
     if (t >= LY / 2) return;  // no block-level synchronization below
-    const int kx = kx0 + blockIdx.y, b = blockIdx.z;
     const int S = 3 * nz, geom = b / bpg;
     const long long sst = (long long)M * LY;
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;

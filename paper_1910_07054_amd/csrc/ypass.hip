@@ -63,18 +63,20 @@ hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M
 {
     (void)QX;
     if (nkx <= 0) return hipSuccess;
-    constexpr int IB = 8;
+    constexpr int IB = 4;
     const int ngrp = (nz + IB - 1) / IB;
-    if (ngrp > 16) return hipErrorInvalidValue;
-    dim3 grid((LY / 2 + 31) / 32, nkx, B);
+    const long long tiles = (long long)((LY / 2 + 31) / 32) * nkx * B;
+    const long long nblk = (tiles + 7) / 8 * 8 * ngrp;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk);
     if (fp64)
-        hipLaunchKernelGGL((k_mix_pairs<double, IB>), grid, dim3(64 * ngrp), 0, s,
+        hipLaunchKernelGGL((k_mix_pairs<double, IB>), grid, dim3(64), 0, s,
                            (const cpx<double>*)Mh, (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs,
-                           QY, (const double*)lp, bpg, adjoint, kx0);
+                           QY, (const double*)lp, bpg, adjoint, kx0, nkx, B);
     else
-        hipLaunchKernelGGL((k_mix_pairs<float, IB>), grid, dim3(64 * ngrp), 0, s,
+        hipLaunchKernelGGL((k_mix_pairs<float, IB>), grid, dim3(64), 0, s,
                            (const cpx<float>*)Mh, (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QY,
-                           (const float*)lp, bpg, adjoint, kx0);
+                           (const float*)lp, bpg, adjoint, kx0, nkx, B);
     return hipGetLastError();
 }
 
