@@ -482,9 +482,11 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
     // the lane offset
     const UniformBuf<R> qb0(Qg, (unsigned)((M + 1) * colstride * sizeof(R)));
     const unsigned off0 = (unsigned)(t + (p == 0 ? 0 : M * colstride));
-    // (above 8 layers the registers do not hold a prefetched row)
+    // (above 8 layers, or with 1024 threads per block, the registers do not
+    // hold a prefetched row)
+    constexpr bool EARLY_ROW = NZMAX <= 8 && NT <= 512;
     TensorRow<R, NZMAX> row0;
-    if constexpr (NZMAX <= 8) {
+    if constexpr (EARLY_ROW) {
         if (kx != 0) {
             if (t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0);
         } else if (t != 0 && t < LY / 2) {
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
         if (kx != 0) {
             auto in = [&](int c, int l) -> cpx<R> { return ld(c, l, ky); };
-            if constexpr (NZMAX <= 8) mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg, row0);
+            if constexpr (EARLY_ROW) mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg, row0);
             else mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg);
             store(ky);
         } else if (t != 0) {
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
                               : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
             };
             // on the rows kx = 0 and kx = M only xx, yy, zz and yz are non-zero
-            if constexpr (NZMAX <= 8) mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg, row0);
+            if constexpr (EARLY_ROW) mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg, row0);
             else mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg);
 #pragma unroll
             for (int k = 0; k < 3 * NZMAX; ++k) {
