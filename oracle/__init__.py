@@ -8,9 +8,10 @@ nothing here is shared with the HIP library.
 Parts:
   * ``newell_oracle.c`` (loaded through ctypes): the Newell kernels f and g in
     extended precision, the generalized tensor of a cuboid pair (Sec. 2 and
-    appendices A/B), layer-pair tables on the lateral lattice, the brute-force
-    field over all cell pairs (Sec. 3), its transpose, and the thickness
-    gradient.
+    appendices A/B), layer-pair tables on the lateral lattice (entries beyond
+    50 cell sizes by quadrature of the dipole kernel, where the closed form
+    has lost its digits), the brute-force field over all cell pairs (Sec. 3),
+    its transpose, and the thickness gradient.
   * ``fft_field``: the hybrid algorithm of Sec. 3.1 (2D discrete Fourier
     transform in x and y, explicit sum over layers in z), written with
     numpy's FFT as the library step, in FP64.
@@ -62,6 +63,8 @@ def _load():
     lib.hfdo_tensor_cuboids.argtypes = [d] * 9 + [p]
     lib.hfdo_dtensor_dZ_cuboids.restype = None
     lib.hfdo_dtensor_dZ_cuboids.argtypes = [d] * 9 + [p]
+    lib.hfdo_tensor_far.restype = None
+    lib.hfdo_tensor_far.argtypes = [d] * 9 + [p]
     lib.hfdo_pair_table.restype = i
     lib.hfdo_pair_table.argtypes = [i, i, d, d, d, d, d, d, p]
     lib.hfdo_pair_dtable.restype = i
@@ -112,6 +115,17 @@ def tensor_cuboids(X, Y, Z, target, source) -> np.ndarray:
     out = np.zeros(6)
     _load().hfdo_tensor_cuboids(float(X), float(Y), float(Z), *map(float, target),
                                 *map(float, source), _ptr(out))
+    return out
+
+
+def tensor_far(X, Y, Z, target, source) -> np.ndarray:
+    """The far-field rule the pair tables use beyond 50 cell sizes: the
+    cell-averaged dipole kernel integrated over both cuboids with 3
+    Gauss-Legendre points per axis, extended precision (same conventions as
+    tensor_cuboids)."""
+    out = np.zeros(6)
+    _load().hfdo_tensor_far(float(X), float(Y), float(Z), *map(float, target), *map(float, source),
+                            _ptr(out))
     return out
 
 

@@ -12,7 +12,13 @@
  * difference that forms a tensor entry cancels catastrophically at large
  * separation (the paper calls the method exact and is silent on floating
  * point); extended precision keeps the cancellation error roughly 2000x below
- * that of an FP64 evaluation.  Field sums are accumulated in FP64.
+ * that of an FP64 evaluation, which is still not enough beyond some fifty
+ * cell sizes.  Layer-pair table entries whose cuboid centres are at least FAR_RHO
+ * times the largest cell dimension apart are therefore taken from the
+ * definition the closed forms integrate: the cell-averaged dipole kernel,
+ * integrated over both cuboids by tensor-product Gauss-Legendre quadrature
+ * (smooth there, so a few points per axis reach rounding level).  Field sums
+ * are accumulated in FP64.
  *
  * Conventions (Sec. 2 of the paper, "Generalized Newell Equation"):
  *   - the tensor N relates a source cuboid at the origin with dimensions
@@ -236,6 +242,102 @@ void hfdo_dtensor_dZ_cuboids(double X, double Y, double Z, double dx, double dy,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Far field: N_kl = -1/(4 pi |tau|) int_tau int_tau' (3 r_k r_l - r^2 d_kl)  */
+/* / r^5, r = x - x', for a target cuboid tau = [X, X+dx] x [Y, Y+dy] x       */
+/* [Z, Z+dz] and a source cuboid tau' = [0, dxs] x [0, dys] x [0, dzs]:      */
+/* FAR_N Gauss-Legendre points per axis on each of the six axes.             */
+/* ------------------------------------------------------------------------ */
+#define FAR_RHO 50.0L
+#define FAR_N 3
+
+/* nodes and weights of the n-point rule on [-1, 1]: Newton iteration on the
+ * Legendre polynomial P_n from the Chebyshev estimate */
+static void gauss_legendre(int n, LD *x, LD *w)
+{
+    for (int i = 0; i < n; ++i) {
+        LD z = cosl(PI_L * (i + 0.75L) / (n + 0.5L)), dp = 0.0L;
+        for (int it = 0; it < 100; ++it) {
+            LD p0 = 1.0L, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                LD p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0L; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0L);
+            LD dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        x[i] = z;
+        w[i] = 2.0L / ((1.0L - z * z) * dp * dp);
+    }
+}
+
+static void quad_far(LD X, LD Y, LD Z, LD dx, LD dy, LD dz, LD dxs, LD dys, LD dzs, LD out[6])
+{
+    LD gx[FAR_N], gw[FAR_N];
+    gauss_legendre(FAR_N, gx, gw);
+    LD acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < FAR_N; ++a)
+    for (int b = 0; b < FAR_N; ++b)
+    for (int c = 0; c < FAR_N; ++c) {
+        const LD xt = X + 0.5L * dx * (1 + gx[a]), yt = Y + 0.5L * dy * (1 + gx[b]),
+                 zt = Z + 0.5L * dz * (1 + gx[c]);
+        const LD wt = gw[a] * gw[b] * gw[c];
+        for (int d = 0; d < FAR_N; ++d)
+        for (int e = 0; e < FAR_N; ++e)
+        for (int f = 0; f < FAR_N; ++f) {
+            const LD rx = xt - 0.5L * dxs * (1 + gx[d]), ry = yt - 0.5L * dys * (1 + gx[e]),
+                     rz = zt - 0.5L * dzs * (1 + gx[f]);
+            const LD r2 = rx * rx + ry * ry + rz * rz;
+            const LD ir5 = 1.0L / (r2 * r2 * sqrtl(r2));
+            const LD w = wt * gw[d] * gw[e] * gw[f] * ir5;
+            acc[0] += w * (3 * rx * rx - r2);
+            acc[1] += w * (3 * ry * ry - r2);
+            acc[2] += w * (3 * rz * rz - r2);
+            acc[3] += w * 3 * rx * ry;
+            acc[4] += w * 3 * rx * rz;
+            acc[5] += w * 3 * ry * rz;
+        }
+    }
+    /* the rule integrates over [-1, 1]^6: Jacobian (dx dy dz dxs dys dzs) / 64 */
+    const LD jac = dx * dy * dz * dxs * dys * dzs / 64.0L;
+    for (int k = 0; k < 6; ++k) out[k] = -acc[k] * jac / (4.0L * PI_L * dx * dy * dz);
+}
+
+void hfdo_tensor_far(double X, double Y, double Z, double dx, double dy, double dz, double dxs,
+                     double dys, double dzs, double *out)
+{
+    LD o[6];
+    quad_far(X, Y, Z, dx, dy, dz, dxs, dys, dzs, o);
+    for (int k = 0; k < 6; ++k) out[k] = (double)o[k];
+}
+
+/* Replace the entries of a pair table (layout below) whose centres are at
+ * least FAR_RHO cell sizes apart by the quadrature values. */
+static void far_entries(int nx, int ny, LD dx, LD dy, LD tb, LD tt, LD sb, LD st, double *table)
+{
+    const int Wo = 2 * nx - 1, Ho = 2 * ny - 1;
+    const LD dz = tt - tb, dzs = st - sb;
+    LD big = dx > dy ? dx : dy;
+    if (dz > big) big = dz;
+    if (dzs > big) big = dzs;
+    const LD Z = tb - sb, zc = Z + 0.5L * dz - 0.5L * dzs;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int qi = 0; qi < Ho; ++qi) {
+        const LD Y = (LD)(qi - (ny - 1)) * dy;
+        for (int pi = 0; pi < Wo; ++pi) {
+            const LD X = (LD)(pi - (nx - 1)) * dx;
+            if (sqrtl(X * X + Y * Y + zc * zc) < FAR_RHO * big) continue;
+            LD o[6];
+            quad_far(X, Y, Z, dx, dy, dz, dx, dy, dzs, o);
+            for (int k = 0; k < 6; ++k) table[(size_t)k * Wo * Ho + (size_t)qi * Wo + pi] = (double)o[k];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Layer-pair tables on the lateral lattice (Sec. 3, equal dx, dy for every  */
 /* cell; each layer has its own thickness).  Translation invariance gives    */
 /* N^{ij}(p, q) for lateral offsets p in [-(nx-1), nx-1], q in [-(ny-1),     */
@@ -322,6 +424,7 @@ int hfdo_pair_table(int nx, int ny, double dx, double dy, double tb, double tt, 
         for (size_t k = 0; k < (size_t)Wo * Ho; ++k) o[k] = (double)(pref * acc[k]);
     }
     free(lat); free(tmp); free(acc);
+    far_entries(nx, ny, dx, dy, tb, tt, sb, st, table);
     return 0;
 }
 

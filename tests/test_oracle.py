@@ -420,6 +420,40 @@ def test_thickness_gradient_uniform_mode_equals_full_mode():
 
 
 # ---------------------------------------------------------------------------
+# Far field of the pair tables: quadrature of the dipole kernel beyond 50
+# cell sizes, where the closed form has lost its digits to cancellation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("R", [50, 120, 500, 2000])
+def test_far_rule_matches_high_order_quadrature(R):
+    tgt, src = (2.0, 1.5, 1.3), (2.0, 1.5, 0.6)
+    X, Y, Z = R * 2.0, 3 * 1.5, 0.7
+    fq = oracle.tensor_far(X, Y, Z, tgt, src)
+    q = oracle.quad_tensor(X, Y, Z, tgt, src, n=12)
+    assert np.abs(fq - q).max() <= 2e-12 * np.abs(q).max()
+
+
+def test_far_rule_matches_newell_where_both_hold():
+    """At 50 cell sizes the extended-precision closed form is still good to
+    ~1e-8 relative, and the two agree there."""
+    tgt, src = (2.0, 2.0, 1.0), (2.0, 2.0, 2.3)
+    X, Y, Z = 45 * 2.0, -20 * 2.0, 1.5
+    nw = oracle.tensor_cuboids(X, Y, Z, tgt, src)
+    fq = oracle.tensor_far(X, Y, Z, tgt, src)
+    assert np.abs(fq - nw).max() <= 1e-7 * np.abs(nw).max()
+
+
+def test_pair_table_uses_far_rule_beyond_50_cells():
+    nx, ny, dx, dy = 70, 3, 2.0, 1.5
+    tab = oracle.pair_table(nx, ny, dx, dy, 0.8, 2.0, 0.0, 0.5)  # target [0.8, 2.0], source [0, 0.5]
+    near = tab[:, ny - 1 + 1, nx - 1 + 10]
+    far = tab[:, ny - 1 - 2, nx - 1 + 60]
+    np.testing.assert_allclose(near, oracle.tensor_cuboids(10 * dx, 1 * dy, 0.8, (dx, dy, 1.2), (dx, dy, 0.5)),
+                               rtol=0, atol=1e-15)
+    np.testing.assert_allclose(far, oracle.tensor_far(60 * dx, -2 * dy, 0.8, (dx, dy, 1.2), (dx, dy, 0.5)),
+                               rtol=0, atol=1e-18)
+
+
+# ---------------------------------------------------------------------------
 # Equidistant case (eq. FFT_3D): the 3-D transform reproduces the direct sum
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx,ny,nz,t,pitch", [(7, 5, 4, 0.8, 1.3), (6, 9, 3, 1.1, 1.1), (5, 4, 1, 0.6, 0.6)])
