@@ -41,6 +41,8 @@ struct XPassShape {
     }
     static constexpr int TY = pick_ty();
     static constexpr size_t LDS = sizeof(cpx<R>) * TY * RS;
+    // waves per SIMD for two resident blocks (the register budget that allows it)
+    static constexpr int WPE = NT / 128 > 8 ? 8 : (NT / 128 < 1 ? 1 : NT / 128);
 };
 
 // ---------------------------------------------------------------------------
@@ -133,7 +135,7 @@ struct RealSplit {
 // group applies to its own row.
 // ---------------------------------------------------------------------------
 template <typename R, int LX>
-__global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
+__global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
                                               int nx, int ny, long long in_sig_stride,
                                               int in_row_stride, const cpx<R>* __restrict__ twx)
 {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xfwd(const R* __res
 // Unnormalized; the 1/(Lx Ly) is folded into the tensor.
 // ---------------------------------------------------------------------------
 template <typename R, int LX>
-__global__ __launch_bounds__((XPassShape<R, LX>::NT)) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
+__global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
                                               int nx, int ny, long long out_sig_stride,
                                               int out_row_stride, const cpx<R>* __restrict__ twx)
 {
