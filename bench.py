@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--nz-sweep", action="store_true",
                     help="also time the explicit layer sum and the equidistant z-FFT path on "
                          "256x256 x nz equal-thickness stacks, nz = 1 .. 64 (Sec. 3.2 scaling)")
+    ap.add_argument("--vjp", action="store_true",
+                    help="also time hfd_demag_vjp (grad m and grad thickness) on the workload, with the "
+                         "derivative tensors recomputed per call and stored")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -238,6 +241,31 @@ def nz_sweep(steps, warmup, stream, nzs=(1, 2, 4, 8, 16, 32, 64)):
             "fit_equidistant_ms": {"a_nzlognz": a2[0], "b": a2[1]}}
 
 
+def time_vjp(wl, m, steps, warmup, stream):
+    """hfd_demag_vjp for L = mean of h_z over the last layer (the free layer of
+    C5) of every state: grad_m and grad_thickness, derivative tensors
+    recomputed per call or stored in the plan; graph replay."""
+    import torch
+    from paper_1910_07054_amd import hfd
+    res = {}
+    gh = torch.zeros_like(m)
+    gh[:, 2, -1] = 1.0 / (wl.nx * wl.ny)
+    for name, fl in (("recomputed", hfd.HFD_FP32), ("stored", hfd.HFD_FP32 | hfd.HFD_STORE_DTENSOR)):
+        t0 = time.perf_counter()
+        plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=wl.batch, flags=fl)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        out = {}
+
+        def run():
+            gm, gt = plan.vjp(m, gh, want_m=True, want_t=True, stream=stream)
+            out["gm"], out["gt"] = gm, gt
+        ms = replay_ms(run, steps, warmup, stream)
+        res[name] = {"ms_per_call": ms, "ms_per_state": ms / wl.batch, "setup_s": setup_s}
+        plan.destroy()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -359,6 +387,8 @@ def main():
         out["path_comparison"] = compare_paths(wl, m, args.steps, args.warmup, stream)
     if args.nz_sweep:
         out["nz_sweep"] = nz_sweep(max(args.steps // 4, 20), args.warmup, stream)
+    if args.vjp:
+        out["vjp"] = time_vjp(wl, m, max(args.steps // 4, 10), args.warmup, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     plan.destroy()
