@@ -123,7 +123,8 @@ def cpu_baseline(wl, target_s=12.0):
         "unit": "evals/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"brute-force FP64 sum (extended-precision tensor tables) for {n2} random target "
+        "sample": (f"brute-force FP64 sum (extended-precision tensor tables, quadrature beyond 50 cell "
+                   f"sizes) for {n2} random target "
                    f"cells of layer 0 against all {cells} source cells, {t_n2:.1f} s incl. "
                    f"{t_tab:.1f} s of pair tables for that layer; extrapolated to {cells} targets "
                    f"= {t_eval:.0f} s per evaluation (tables excluded)"),
