@@ -108,22 +108,23 @@ struct hfd_plan_s {
     void* Hh = nullptr;
     size_t x1_bytes = 0, mh_bytes = 0;
     // thickness-derivative data
-    void* D = nullptr;          // [G or 1][nzeta_max][6][QX][QY] plan precision
+    void* D = nullptr;          // [G or 1][QX][nzeta_max][6][QY] plan precision
     long long d_geom_stride = 0;  // elements per geometry
     int d_geoms = 0;            // geometries D holds (G when stored, else 1)
-    int* zidx = nullptr;        // [G][nz][nz][4] index of zeta per ordered pair
+    int* itab = nullptr;        // [G][itab_stride] interface positions and D slots (k_tgrad)
+    int itab_stride = 0;
     double* zeta_dev = nullptr; // [G][nzeta_max]
     int nzeta_max = 0;
     std::vector<int> nzeta;     // per geometry
     std::vector<double> zeta_host;
-    std::vector<int> zidx_host;
+    std::vector<int> itab_host;
     bool d_valid = false;       // D holds the current geometry (stored mode)
     double* dW = nullptr;       // FP64 scratch for the derivative transform
     void* dF = nullptr;
     double* dscale = nullptr;   // -1/(Lx Ly) per zeta of a chunk
     int dchunk = 0;
-    double* partial = nullptr;  // reduction partials [batch_max][nblk][2 nz]
-    int nblk = 0;
+    double* partial = nullptr;  // reduction partials [batch_max][ntiles][2 nz]
+    int ntiles = 0;
     // equidistant stack: layer sum by FFT along z (path 4)
     bool eq3d = false;
     int Lz = 0;                 // padded length along z
@@ -215,7 +216,7 @@ void free_plan_memory(hfd_plan p)
     if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
-                    p->D, p->zidx, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz};
+                    p->D, p->itab, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
@@ -224,7 +225,7 @@ void free_plan_memory(hfd_plan p)
     p->Q = p->lp = p->twx = p->twy = p->X1 = p->Mh = p->Hh = nullptr;
     p->twx64 = p->twy64 = nullptr;
     p->D = nullptr;
-    p->zidx = nullptr;
+    p->itab = nullptr;
     p->zeta_dev = nullptr;
     p->partial = nullptr;
     p->Bc = p->twz = nullptr;
@@ -362,7 +363,7 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
                 const int k = uid[pu];
                 if (k < u0 || k >= u0 + np) continue;
                 hipError_t e = launch_pack(p->fp64, F + (size_t)(k - u0) * fstride, qdst, scale + pu, 1, 5,
-                                           p->M, p->Ly, p->QX, p->QY, pu, p->P, s);
+                                           p->M, p->Ly, p->QX, p->QY, pu, p->P, 1, s);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
@@ -416,7 +417,7 @@ hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
     if (st == HFD_OK)
         st = tensor_spectra(p, geos, s, [&](int u0, int np, const double* F) -> hipError_t {
             return launch_pack(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->Ly, p->QX,
-                               p->QY, 0, np, s);
+                               p->QY, 0, np, 0, s);
         });
     if (st == HFD_OK) {
         hipError_t e = launch_zdft3(p->fp64, Q2, p->Q, p->nz, p->Lz, p->QX, p->QY, s);
@@ -449,31 +450,29 @@ hfd_status check_equidistant(int nz, int G, const std::vector<double>& t, const 
 
 
 // Distinct z offsets zeta = (interface of the target) - (interface of the
-// source) over all ordered layer pairs, merged when equal to 1e-12 relative.
-void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>& zidx,
+// source) over all ordered layer pairs, merged when equal to 1e-12 relative,
+// and per geometry the table of k_tgrad: interface positions (top_l and
+// bot_{l+1} merged when they touch), their ranks, the position of every
+// layer's bottom and top, and the D slot of z_p - z_q for every position pair.
+void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>& itab,
                         std::vector<int>& count, int& nmax)
 {
     const int nz = p->nz, G = p->G;
+    const ITabLayout lay = itab_layout(nz);
+    const int stride = lay.stride;
     std::vector<std::vector<double>> per(G);
-    zidx.assign((size_t)G * nz * nz * 4, 0);
+    itab.assign((size_t)G * stride, 0);
     count.assign(G, 0);
     nmax = 0;
     for (int g = 0; g < G; ++g) {
         const double* t = &p->thick[(size_t)g * nz];
         const double* z = &p->zbot[(size_t)g * nz];
         std::vector<double> all;
-        auto zs = [&](int i, int j, int c) {
-            const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
-            switch (c) {
-            case 0: return ti - bj;
-            case 1: return bi - bj;
-            case 2: return ti - tj;
-            default: return bi - tj;
-            }
-        };
         for (int i = 0; i < nz; ++i)
-            for (int j = 0; j < nz; ++j)
-                for (int c = 0; c < 4; ++c) all.push_back(zs(i, j, c));
+            for (int j = 0; j < nz; ++j) {
+                const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
+                all.insert(all.end(), {ti - bj, bi - bj, ti - tj, bi - tj});
+            }
         std::vector<double> u = all;
         std::sort(u.begin(), u.end());
         std::vector<double> m;
@@ -484,18 +483,39 @@ void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>&
         // snap values within rounding of zero to exactly zero (touching interfaces)
         double scale = 0.0;
         for (int l = 0; l < nz; ++l) scale = std::max(scale, std::fabs(z[l]) + t[l]);
+        const double ztol = 1e-12 * std::max(1.0, scale);
         for (double& v : m)
-            if (std::fabs(v) <= 1e-12 * std::max(1.0, scale)) v = 0.0;
-        for (int i = 0; i < nz; ++i)
-            for (int j = 0; j < nz; ++j)
-                for (int c = 0; c < 4; ++c) {
-                    const double v = zs(i, j, c);
-                    int best = 0;
-                    double bd = 1e300;
-                    for (int k = 0; k < (int)m.size(); ++k)
-                        if (std::fabs(m[k] - v) < bd) { bd = std::fabs(m[k] - v); best = k; }
-                    zidx[(((size_t)g * nz + i) * nz + j) * 4 + c] = best;
-                }
+            if (std::fabs(v) <= ztol) v = 0.0;
+        auto nearest = [&](double v) {
+            int best = 0;
+            double bd = 1e300;
+            for (int k = 0; k < (int)m.size(); ++k)
+                if (std::fabs(m[k] - v) < bd) { bd = std::fabs(m[k] - v); best = k; }
+            return best;
+        };
+        // interface positions bottom to top
+        int* tab = &itab[(size_t)g * stride];
+        int* pinfo = tab + lay.info;
+        int* pbot = tab + lay.pbot;
+        int* ptop = tab + lay.ptop;
+        int* zpq = tab + lay.zpq;
+        std::vector<double> pz;
+        for (int l = 0; l < nz; ++l) {
+            if (l > 0 && std::fabs(z[l] - pz.back()) <= ztol) {
+                pinfo[pz.size() - 1] |= 2;  // bottom of l on the top of l - 1 (rank l)
+            } else {
+                pinfo[pz.size()] = l * 4 + 2;
+                pz.push_back(z[l]);
+            }
+            pbot[l] = (int)pz.size() - 1;
+            pinfo[pz.size()] = (l + 1) * 4 + 1;
+            ptop[l] = (int)pz.size();
+            pz.push_back(z[l] + t[l]);
+        }
+        const int NI = (int)pz.size();
+        tab[0] = NI;
+        for (int a = 0; a < NI; ++a)
+            for (int c = 0; c < NI; ++c) zpq[a * lay.nsp + c] = nearest(pz[a] - pz[c]);
         per[g] = m;
         count[g] = (int)m.size();
         nmax = std::max(nmax, (int)m.size());
@@ -509,9 +529,9 @@ void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>&
 hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
 {
     std::vector<double> zeta;
-    std::vector<int> zidx, count;
+    std::vector<int> itab, count;
     int nmax = 0;
-    derivative_offsets(p, zeta, zidx, count, nmax);
+    derivative_offsets(p, zeta, itab, count, nmax);
     const bool store = p->flags & HFD_STORE_DTENSOR;
     const int dgeoms = store ? p->G : 1;
     const long long per_geom = (long long)nmax * 6 * p->QX * p->QY;
@@ -526,7 +546,8 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
         p->d_geom_stride = per_geom;
         p->d_geoms = dgeoms;
     }
-    if (!p->zidx) HFD_TRY(dev_alloc(&p->zidx, sizeof(int) * zidx.size(), "offset index"));
+    if (!p->itab) HFD_TRY(dev_alloc(&p->itab, sizeof(int) * itab.size(), "interface table"));
+    p->itab_stride = itab_layout(p->nz).stride;
     const long long plane = (long long)p->Lx * p->Ly;
     const long long per_z = 6 * plane * 8;
     const int chunk = (int)std::max(1LL, std::min<long long>(nmax, (256LL << 20) / per_z));
@@ -545,20 +566,20 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
         p->dchunk = chunk;
     }
     p->zeta_host = zeta;
-    p->zidx_host = zidx;
+    p->itab_host = itab;
     p->nzeta = count;
     HFD_HIP(hipMemcpyAsync(p->zeta_dev, p->zeta_host.data(), sizeof(double) * zeta.size(),
                            hipMemcpyHostToDevice, s));
-    HFD_HIP(hipMemcpyAsync(p->zidx, p->zidx_host.data(), sizeof(int) * zidx.size(),
+    HFD_HIP(hipMemcpyAsync(p->itab, p->itab_host.data(), sizeof(int) * itab.size(),
                            hipMemcpyHostToDevice, s));
     // partial sums of the reduction
-    const int nblk = (int)(((long long)p->M * p->Ly + 255) / 256);
-    if (nblk != p->nblk || !p->partial) {
+    const int ntiles = tgrad_tiles(p->M, p->Ly);
+    if (ntiles != p->ntiles || !p->partial) {
         if (p->partial) (void)hipFree(p->partial);
         p->partial = nullptr;
-        HFD_TRY(dev_alloc(&p->partial, sizeof(double) * (size_t)p->batch_max * nblk * 2 * p->nz,
+        HFD_TRY(dev_alloc(&p->partial, sizeof(double) * (size_t)p->batch_max * ntiles * 2 * p->nz,
                           "reduction partials"));
-        p->nblk = nblk;
+        p->ntiles = ntiles;
     }
     HFD_HIP(hipStreamSynchronize(s));
     p->d_valid = false;
@@ -579,8 +600,8 @@ hfd_status compute_derivatives(hfd_plan p, int g, int slot, hipStream_t s)
                                     p->ny, p->Lx, p->Ly, p->dx, p->dy, s));
         HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));
         HFD_HIP(launch_yfwd(true, p->Ly, p->dF, p->dF, p->Ly, (long long)nc * 6 * p->M, p->twy64, s));
-        HFD_HIP(launch_pack(p->fp64, p->dF, dst + (size_t)z0 * 6 * p->QX * p->QY * p->rsz, p->dscale,
-                            nc, 6, p->M, p->Ly, p->QX, p->QY, 0, 0, s));
+        HFD_HIP(launch_pack(p->fp64, p->dF, dst, p->dscale, nc, 6, p->M, p->Ly, p->QX, p->QY, z0,
+                            p->nzeta_max, 1, s));
     }
     return HFD_OK;
 }
@@ -877,18 +898,21 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     const int bpg = batch / p->G;
     if (p->d_valid) {
         HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
-                             p->D, p->d_geom_stride, p->zidx, 0, p->lp, bpg, p->QX, p->QY, p->partial,
-                             p->nblk, s));
+                             p->D, p->d_geom_stride, p->nzeta_max, p->itab, p->itab_stride, 0, p->lp,
+                             bpg, p->QX,
+                             p->QY, p->partial, s));
     } else {
         // recompute the derivative tensor of one stack at a time
         for (int g = 0; g < p->G; ++g) {
             HFD_TRY(compute_derivatives(p, g, 0, s));
             HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g * bpg, bpg, p->Q,
-                                 p->q_geom_stride, p->D, p->d_geom_stride, p->zidx, g, p->lp, bpg,
-                                 p->QX, p->QY, p->partial, p->nblk, s));
+                                 p->q_geom_stride, p->D, p->d_geom_stride, p->nzeta_max, p->itab,
+                                 p->itab_stride,
+                                 g, p->lp, bpg, p->QX, p->QY, p->partial, s));
         }
     }
-    HFD_HIP(launch_tgrad_finish(p->partial, p->nblk, batch, p->nz, grad_thickness, s));
+    HFD_HIP(launch_tgrad_finish(p->partial, p->ntiles, batch, p->nz, p->itab, p->itab_stride, bpg,
+                                grad_thickness, s));
     return HFD_OK;
 }
 

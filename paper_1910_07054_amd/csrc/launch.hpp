@@ -50,13 +50,35 @@ hipError_t launch_zdft3(bool out_fp64, const double* Q2, void* T3, int nz, int L
 hipError_t launch_eq3d_mix(bool fp64, int LZ, void* Mh, void* Bc, void* Hh, void* HBc, int nz, int M,
                            int LY, int B, const void* T3, int QY, const void* twz, hipStream_t s);
 
-// thickness-gradient reduction over the spectra (states b0 .. b0+nb-1)
+// thickness-gradient reduction over the spectra (states b0 .. b0+nb-1, nb a
+// multiple of bpg); partial: [states][tgrad_tiles(M, LY)][2 nz]
+int tgrad_tiles(int M, int LY);
+// Per-geometry interface table of the thickness gradient (ints): [0] NI, the
+// number of interface positions; pinfo[nsp] at `info` (rank r*4 + 1 if the top
+// of layer r-1 is there + 2 if the bottom of layer r is there); pos_bot[nz],
+// pos_top[nz]; zpq[nsp][nsp] at `zpq`, the D slot of z_p - z_q.  nsp = 2nz
+// rounded up to 8 and every row 32-byte aligned, so a chunk of 8 entries is
+// two aligned 16-byte loads; padding entries are slot 0.
+struct ITabLayout {
+    int nsp, info, pbot, ptop, zpq, stride;
+};
+__host__ __device__ inline ITabLayout itab_layout(int nz)
+{
+    ITabLayout t;
+    t.nsp = (2 * nz + 7) & ~7;
+    t.info = 8;
+    t.pbot = t.info + t.nsp;
+    t.ptop = t.pbot + nz;
+    t.zpq = (t.ptop + nz + 7) & ~7;
+    t.stride = t.zpq + t.nsp * t.nsp;
+    return t;
+}
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, long long dgs,
-                        const int* zidx, int g_first, const void* lp, int bpg, int QX, int QY,
-                        double* partial, int nblk, hipStream_t s);
-hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, double* grad_t,
-                               hipStream_t s);
+                        int nb, const void* Q, long long qgs, const void* D, long long dgs, int nzt,
+                        const int* itab, int itab_stride, int g_first, const void* lp, int bpg,
+                        int QX, int QY, double* partial, hipStream_t s);
+hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const int* itab,
+                               int itab_stride, int bpg, double* grad_t, hipStream_t s);
 
 // tensor setup (FP64)
 struct PairGeoH {
@@ -72,6 +94,6 @@ hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx,
 // comps 6: derivative tables, [npairs][6][QX][QY]
 hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
                        int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
-                       hipStream_t s);
+                       int row_outer, hipStream_t s);
 
 }  // namespace hfd

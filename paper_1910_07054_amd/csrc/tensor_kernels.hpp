@@ -381,11 +381,13 @@ __global__ __launch_bounds__(128) void k_dtensor_real(double* __restrict__ W,
 // components, imaginary part for the odd-even ones, times scale[pair].
 // comps: number of stored components per pair (5: xx, yy, xy, xz, yz;
 // 6: all); the source has 6 arrays per pair in the order xx yy zz xy xz yz.
+// row_outer: output [kx][pair_total][comps][ky] with this call's pairs at
+// pair0 (each kx row of a table contiguous); else [pair][comp][kx][ky].
 template <typename R>
 __global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F, R* __restrict__ Qout,
                                               const double* __restrict__ scale, int npairs, int comps,
                                               int M, int Ly, int QX, int QY, int pair0,
-                                              int pair_total)
+                                              int pair_total, int row_outer)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)comps * QX * QY;
@@ -405,10 +407,8 @@ __global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F,
         val = Fs[(long long)kx * Ly + ky];
     }
     const bool imag = (c6 == 4 || c6 == 5);
-    // comps == 5 (field tensor): [kx][pair][comp][ky] with pair_total pairs per
-    // column; comps == 6 (derivative tables): [pair][comp][kx][ky]
-    const long long o = comps == 5
-        ? (((long long)kx * pair_total + pair0 + u) * 5 + c) * QY + ky
+    const long long o = row_outer
+        ? (((long long)kx * pair_total + pair0 + u) * comps + c) * QY + ky
         : idx;
     Qout[o] = (R)((imag ? val.y : val.x) * scale[u]);
 }

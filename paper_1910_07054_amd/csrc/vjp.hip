@@ -6,15 +6,26 @@
 // interfaces bot_i, top_i (target) and bot_j, top_j (source) through
 // N = -1/(4 pi dx dy t_i) sum_c s_c Psi(zeta_c), zeta = {top_i - bot_j,
 // bot_i - bot_j, top_i - top_j, bot_i - top_j}, s = {+1, -1, -1, +1}, Psi the
-// lateral-stencilled Phi.  With D(zeta) the normalized DFT of
-// -1/(4 pi dx dy) dPsi/dz (zeta):
-//   dT/dtop_i = -T/t_i + (D(z0) - D(z2))/t_i     dT/dbot_i = T/t_i + (D(z3) - D(z1))/t_i
-//   dT/dtop_j = (D(z2) - D(z3))/t_i             dT/dbot_j = (D(z1) - D(z0))/t_i
-// Each interface gradient is a sum over frequencies and ordered pairs of
-// P[X] = Re sum_cc' X_cc' conj(G_i,c) M_j,c'.  The half spectrum holds
+// lateral-stencilled Phi.  The sign s_c factors into a target sign (+1 top,
+// -1 bottom) times a source sign (+1 bottom, -1 top), so with K(zeta) the
+// normalized DFT of -Psi/(4 pi dx dy) and, per interface e of layer l,
+//   Ghat_e = +-G_l / t_l (+ top, - bottom),  Mhat_e = -+M_l (- top, + bottom),
+// the functional is a sum over interface pairs:
+//   L = sum_{e,f} Re conj(Ghat_e) . K(z_e - z_f) Mhat_f.
+// Interfaces that coincide (top_l touching bot_{l+1}) move together under
+// every thickness change (gaps are fixed), so they are merged into one
+// position p with summed Ghat_p, Mhat_p.  Moving position p alone changes L by
+//   dL/dz_p = sum_q [P(p, q) - P(q, p)] + (1/t terms),
+//   P(p, q) = Re conj(Ghat_p) . D(z_p - z_q) Mhat_q,
+// D = dK/dzeta the normalized DFT of -1/(4 pi dx dy) dPsi/dz.  The 1/t_l
+// factor of Ghat adds -L_l / t_l to the top of layer l and +L_l / t_l to its
+// bottom, L_l = sum_j Re conj(G_l) . T^{lj} M_j the layer's share of L.  Each
+// D(z_p - z_q) is read once per frequency, where a sum over ordered layer pairs
+// and their four offsets reads it up to eight times.  The half spectrum holds
 // kx in [1, M) once (weight 2, the mirror -kx is the complex conjugate) and
 // the packed column 0 carries kx = 0 and kx = Lx/2 (weight 1 each).
-// Stacks keep their gaps: d bot_l/dt_k = [k < l], d top_l/dt_k = [k <= l].
+// Position p has rank r_p (r = l for bot_l, l + 1 for top_l) and
+// dz_p/dt_k = [k < r_p].
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -22,40 +33,11 @@ namespace hfd {
 
 namespace {
 
-// Re sum_cc' A_cc' X_cc' for a symmetric tensor block A given on the quadrant:
-// real components (xx, yy, zz, xy), imaginary ones (xz, yz) given as q with
-// A = i q.  X_cc' = conj(g_c) m_c'.
-template <typename R>
-struct Cross {
-    // symmetric combinations of X: xx, yy, zz, (xy + yx), (xz + zx), (yz + zy)
-    double re[6], im[6];
-};
-
-template <typename R>
-__device__ inline Cross<R> cross_spectrum(const cpx<R> g[3], const cpx<R> m[3])
+// sum over the 64 lanes, the same bits in every lane (xor butterfly)
+__device__ inline double wave_sum(double v)
 {
-    Cross<R> X;
-    auto cr = [&](int a, int b, double& re, double& im) {
-        // conj(g_a) m_b
-        re = (double)g[a].x * m[b].x + (double)g[a].y * m[b].y;
-        im = (double)g[a].x * m[b].y - (double)g[a].y * m[b].x;
-    };
-    double r1, i1, r2, i2;
-    cr(0, 0, X.re[0], X.im[0]);
-    cr(1, 1, X.re[1], X.im[1]);
-    cr(2, 2, X.re[2], X.im[2]);
-    cr(0, 1, r1, i1); cr(1, 0, r2, i2); X.re[3] = r1 + r2; X.im[3] = i1 + i2;
-    cr(0, 2, r1, i1); cr(2, 0, r2, i2); X.re[4] = r1 + r2; X.im[4] = i1 + i2;
-    cr(1, 2, r1, i1); cr(2, 1, r2, i2); X.re[5] = r1 + r2; X.im[5] = i1 + i2;
-    return X;
-}
-
-// contraction with real parts a[0..3] (xx, yy, zz, xy) and imaginary q[4..5]
-template <typename R>
-__device__ inline double contract(const Cross<R>& X, double xx, double yy, double zz, double xy,
-                                  double xz, double yz)
-{
-    return xx * X.re[0] + yy * X.re[1] + zz * X.re[2] + xy * X.re[3] - xz * X.im[4] - yz * X.im[5];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 template <typename T>
@@ -73,153 +55,291 @@ __device__ inline T block_sum(T v, T* red)
     return s;  // valid in thread 0
 }
 
+// Re conj(g) . A m for the symmetric block A with real xx, yy, zz, xy and
+// imaginary i xz, i yz entries; g, m = (re, im) x 3, arithmetic in double.
+template <typename T>
+__device__ inline double gAm(const double g[6], double xx, double yy, double zz, double xy,
+                             double xz, double yz, const T mm[6])
+{
+    const double m[6] = {mm[0], mm[1], mm[2], mm[3], mm[4], mm[5]};
+    const double vxr = xx * m[0] + xy * m[2] - xz * m[5];
+    const double vxi = xx * m[1] + xy * m[3] + xz * m[4];
+    const double vyr = xy * m[0] + yy * m[2] - yz * m[5];
+    const double vyi = xy * m[1] + yy * m[3] + yz * m[4];
+    const double vzr = zz * m[4] - xz * m[1] - yz * m[3];
+    const double vzi = zz * m[5] + xz * m[0] + yz * m[2];
+    return g[0] * vxr + g[1] * vxi + g[2] * vyr + g[3] * vyi + g[4] * vzr + g[5] * vzi;
+}
+
 }  // namespace
 
-// One thread per (state b, spectrum point).  pass 0 accumulates the terms of the
-// target layer's interfaces (outer index = target i), pass 1 those of the
-// source layer's interfaces (outer index = source j).
-// Output partial[b][blk][2 nz]: (d/dbot_l, d/dtop_l) per layer, per block.
-template <typename R>
-__global__ __launch_bounds__(256) void k_tgrad(const cpx<R>* __restrict__ Mh,
-                                               const cpx<R>* __restrict__ Gh, int nz, int M, int LY,
-                                               const R* __restrict__ Q, long long qgs,
-                                               const R* __restrict__ D, long long dgs,
-                                               const int* __restrict__ zidx, int g_first,
-                                               const R* __restrict__ lp, int bpg, int QX, int QY,
-                                               int b0, double* __restrict__ partial)
+// QC = 8 consecutive table entries from a 32-byte aligned address
+template <int QC>
+__device__ inline void load8(const int* __restrict__ src, int (&dst)[QC])
 {
-    __shared__ double red[16];
-    const int b = b0 + blockIdx.y;
+    static_assert(QC == 8, "interface chunks hold 8 positions");
+    const int4 a = reinterpret_cast<const int4*>(src)[0], b = reinterpret_cast<const int4*>(src)[1];
+    dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
+    dst[4] = b.x; dst[5] = b.y; dst[6] = b.z; dst[7] = b.w;
+}
+
+// Per-position gradient sums of one wave over its 64 frequencies of row kx
+// (PACKED: the packed column, rows 0 and M from the unpacked pair A, B).
+// Every load of an iteration is issued without a branch in between: the
+// two layers of a position are always read (clamped index, weight 0 when
+// absent) and source slots past NI read the table's padding slot 0 against
+// Mhat = 0.
+template <typename R, int QC, bool PACKED>
+__device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __restrict__ gb,
+                                 long long sst, int nz, int M, int kx, int ky, int kyn, int kq,
+                                 double sgy, double wgt0, const R* __restrict__ Qg,
+                                 const R* __restrict__ Dg, int nzt, const int* __restrict__ it,
+                                 const R* __restrict__ lpg, int QY, double* __restrict__ acc)
+{
+    const int lane = threadIdx.x;
+    const int P = nz * (nz + 1) / 2;
+    const ITabLayout lay = itab_layout(nz);
+    const int NI = it[0];
+    const int* pinfo = it + lay.info;
+    const int* pbot = it + lay.pbot;
+    const int* ptop = it + lay.ptop;
+    const int* zpq = it + lay.zpq;
+    // acc[v][64]: lane-owned partial sums of position v (LDS, fire-and-forget adds)
+    auto add_out = [&](int v, double val) { atomicAdd(&acc[v * 64 + lane], val); };
+    for (int ps = 0; ps < (PACKED ? 2 : 1); ++ps) {
+        const int row = PACKED ? (ps ? M : 0) : kx;
+        const R* Drow = Dg + (long long)row * nzt * 6 * QY + kq;  // D: [QX][nzt][6][QY]
+        // spectrum (re, im) of component c of layer l at this point
+        auto spec = [&](const cpx<R>* base, int c, int l, double& re, double& im) {
+            const cpx<R> z1 = base[(c * nz + l) * sst + ky];
+            if (!PACKED) {
+                re = z1.x;
+                im = z1.y;
+            } else {
+                const cpx<R> z2 = base[(c * nz + l) * sst + kyn];
+                const double ar = 0.5 * ((double)z1.x + z2.x), ai = 0.5 * ((double)z1.y - z2.y);
+                const double br = 0.5 * ((double)z1.y + z2.y), bi = 0.5 * ((double)z2.x - z1.x);
+                re = ps ? br : ar;
+                im = ps ? bi : ai;
+            }
+        };
+        // interface pairs, sources in chunks of QC held in registers
+        for (int qc = 0; qc < NI; qc += QC) {
+            R mh[QC][6];  // Mhat in plan precision
+            int pi[QC];
+            load8(pinfo + qc, pi);
+#pragma unroll
+            for (int q = 0; q < QC; ++q) {
+                const bool live = qc + q < NI;
+                const int info = pi[q], rk = info >> 2;
+                const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
+                const double wa = live && (info & 1) ? -1.0 : 0.0;  // top of rk - 1: -M
+                const double wb = live && (info & 2) ? 1.0 : 0.0;   // bottom of rk: +M
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double ra, ia, rb, ib;
+                    spec(mb, c, la, ra, ia);
+                    spec(mb, c, lb, rb, ib);
+                    mh[q][2 * c] = (R)(wa * ra + wb * rb);
+                    mh[q][2 * c + 1] = (R)(wa * ia + wb * ib);
+                }
+            }
+            double gq[QC];
+#pragma unroll
+            for (int q = 0; q < QC; ++q) gq[q] = 0.0;
+            for (int p = 0; p < NI; ++p) {
+                const int info = pinfo[p], rk = info >> 2;
+                const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
+                // top of rk - 1: +G / t; bottom of rk: -G / t (lp holds 1/t)
+                const double wa = (info & 1) ? wgt0 * (double)lpg[la] : 0.0;
+                const double wb = (info & 2) ? -wgt0 * (double)lpg[lb] : 0.0;
+                double gh[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double ra, ia, rb, ib;
+                    spec(gb, c, la, ra, ia);
+                    spec(gb, c, lb, rb, ib);
+                    gh[2 * c] = wa * ra + wb * rb;
+                    gh[2 * c + 1] = wa * ia + wb * ib;
+                }
+                int zi[QC];
+                load8(zpq + p * lay.nsp + qc, zi);
+                double ga = 0.0;
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const R* d = Drow + zi[q] * 6 * QY;
+                    const double pd = gAm(gh, d[0], d[QY], d[2 * QY], sgy * (double)d[3 * QY],
+                                          d[4 * QY], sgy * (double)d[5 * QY], mh[q]);
+                    ga += pd;
+                    gq[q] -= pd;
+                }
+                add_out(p, ga);
+            }
+#pragma unroll
+            for (int q = 0; q < QC; ++q)
+                if (qc + q < NI) add_out(qc + q, gq[q]);
+        }
+        // the 1/t_l factor: top_l gets -L_l / t_l, bot_l gets +L_l / t_l; the
+        // stored blocks are t_i T^{ij}
+        for (int l = 0; l < nz; ++l) {
+            const double it_l = lpg[l];  // lp holds 1/t
+            const double w = wgt0 * it_l * it_l;
+            double g6[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double re, im;
+                spec(gb, c, l, re, im);
+                g6[2 * c] = w * re;
+                g6[2 * c + 1] = w * im;
+            }
+            double sl = 0.0;
+#pragma unroll 4
+            for (int j = 0; j < nz; ++j) {
+                const int a = l < j ? l : j, bq = l < j ? j : l;
+                const int u = a * nz - a * (a - 1) / 2 + (bq - a);
+                const R* q = Qg + ((long long)row * P + u) * 5 * QY + kq;
+                const double simag = l <= j ? 1.0 : -1.0;
+                const double xx = q[0], yy = q[QY];
+                const double zz = -(xx + yy) + (l == j ? (double)lpg[nz + l] : 0.0);
+                double m6[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) spec(mb, c, j, m6[2 * c], m6[2 * c + 1]);
+                sl += gAm(g6, xx, yy, zz, sgy * (double)q[2 * QY], simag * (double)q[3 * QY],
+                          simag * sgy * (double)q[4 * QY], m6);
+            }
+            add_out(ptop[l], -sl);
+            add_out(pbot[l], sl);
+        }
+    }
+}
+
+// One wave per (state, kx, 32 lateral frequency pairs): lanes 2s and 2s+1 take
+// ky = t and LY - t (t = ty*32 + s; lane 2s+1 of t = 0 takes ky = LY/2), which
+// share every quadrant value of D and Q.  Each lane accumulates its own
+// per-position sums in LDS; the block sums them over the lanes at the end.
+// Blocks of one kx tile and the bpg states that share a geometry are 8 block
+// indices apart, so they run on one XCD and read the geometry's D and Q
+// through its L2.
+// itab per geometry: see itab_layout.  D per geometry: [QX][nzt][6][QY], nzt D slots per row.
+// lp per geometry: 1/t_l, then the trace term of the diagonal blocks.
+// partial[b][tile][2nz]: the block's position gradients.
+template <typename R, int QC>
+__global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
+                                              const cpx<R>* __restrict__ Gh, int nz, int M, int LY,
+                                              const R* __restrict__ Q, long long qgs,
+                                              const R* __restrict__ D, long long dgs, int nzt,
+                                              const int* __restrict__ itab, int itab_stride,
+                                              int g_first, const R* __restrict__ lp, int bpg,
+                                              int QY, int b0, int ntiles,
+                                              double* __restrict__ partial)
+{
+    const int L = blockIdx.x, r8 = L >> 3;
+    const int ntile8 = (ntiles + 7) >> 3;
+    const int sg = r8 % bpg, rest = r8 / bpg;
+    const int tile = (rest % ntile8) * 8 + (L & 7);
+    if (tile >= ntiles) return;
+    const int b = b0 + (rest / ntile8) * bpg + sg;
     const int geom = b / bpg;
-    const long long npts = (long long)M * LY;
-    const long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = pt < npts;
-    const int kx = active ? (int)(pt / LY) : 0, ky = active ? (int)(pt % LY) : 0;
+    const int half = LY >> 1;
+    const int tpk = (half + 31) >> 5;
+    const int kx = tile / tpk, ty = tile - kx * tpk;
+    const int lane = threadIdx.x;
+    const int t0 = ty * 32 + (lane >> 1);
+    const bool active = t0 < half;
+    const int t = active ? t0 : 0;
+    const int ky = (lane & 1) == 0 ? t : (t == 0 ? half : LY - t);
+    const int kq = ky <= half ? ky : LY - ky;
+    const double sgy = ky <= half ? 1.0 : -1.0;
+    const int kyn = (LY - ky) & (LY - 1);
     const int S = 3 * nz;
     const long long sst = (long long)M * LY;
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;
     const cpx<R>* gb = Gh + ((long long)b * S * M + kx) * LY;
     const R* Qg = Q + (long long)geom * qgs;
     const R* Dg = D + (long long)(geom - g_first) * dgs;
-    const int* zg = zidx + (long long)geom * nz * nz * 4;
     const R* lpg = lp + (long long)geom * 2 * nz;
-    const long long cs = (long long)QX * QY;
-    const int half = LY / 2;
-    const int kq = ky <= half ? ky : LY - ky;
-    const double sgy = ky <= half ? 1.0 : -1.0;
-    const int kyn = (LY - ky) & (LY - 1);
-    const int npts_here = (kx == 0) ? 2 : 1;
-    const double wgt = (kx == 0) ? 1.0 : 2.0;
-    double* out = partial + ((long long)b * gridDim.x + blockIdx.x) * 2 * nz;
-
-    // spectrum of signal (c, l) at this point; p selects A (kx = 0) or B (kx = Lx/2)
-    auto spec = [&](const cpx<R>* base, int c, int l, int p) -> cpx<R> {
-        const cpx<R> z1 = base[(c * nz + l) * sst + ky];
-        if (kx != 0) return z1;
-        const cpx<R> z2 = base[(c * nz + l) * sst + kyn];
-        return p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
-                      : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
-    };
-
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int o = 0; o < nz; ++o) {
-            double acc_bot = 0.0, acc_top = 0.0;
-            if (active) {
-                for (int k = 0; k < nz; ++k) {
-                    const int i = pass == 0 ? o : k, j = pass == 0 ? k : o;
-                    const double ti = 1.0 / (double)lpg[i];
-                    for (int p = 0; p < npts_here; ++p) {
-                        const int row = (kx == 0) ? (p == 0 ? 0 : M) : kx;
-                        cpx<R> g3[3], m3[3];
-                        for (int c = 0; c < 3; ++c) {
-                            g3[c] = spec(gb, c, i, p);
-                            m3[c] = spec(mb, c, j, p);
-                        }
-                        const Cross<R> X = cross_spectrum<R>(g3, m3);
-                        const int* zz4 = zg + (i * nz + j) * 4;
-                        double PD[4];
-                        for (int c = 0; c < 4; ++c) {
-                            const int zi = zz4[c];
-                            const R* d = Dg + (long long)zi * 6 * cs + (long long)row * QY + kq;
-                            PD[c] = contract<R>(X, d[0], d[cs], d[2 * cs], sgy * (double)d[3 * cs],
-                                                d[4 * cs], sgy * (double)d[5 * cs]);
-                        }
-                        double PT = 0.0;
-                        if (pass == 0) {
-                            const int a = i < j ? i : j, bq = i < j ? j : i;
-                            const int u = a * nz - a * (a - 1) / 2 + (bq - a);
-                            const R* q = Qg + ((long long)row * (nz * (nz + 1) / 2) + u) * 5 * QY + kq;
-                            const double simag = i <= j ? 1.0 : -1.0;
-                            const double xx = q[0], yy = q[QY], xy = sgy * (double)q[2 * QY];
-                            const double xz = simag * (double)q[3 * QY];
-                            const double yz = simag * sgy * (double)q[4 * QY];
-                            const double zz = -(xx + yy) + (i == j ? (double)lpg[nz + i] : 0.0);
-                            // stored blocks are t_i T^{ij}
-                            PT = contract<R>(X, xx, yy, zz, xy, xz, yz) / ti;
-                        }
-                        if (pass == 0) {
-                            acc_top += wgt * (-PT + PD[0] - PD[2]) / ti;
-                            acc_bot += wgt * (PT + PD[3] - PD[1]) / ti;
-                        } else {
-                            acc_top += wgt * (PD[2] - PD[3]) / ti;
-                            acc_bot += wgt * (PD[1] - PD[0]) / ti;
-                        }
-                    }
-                }
-            }
-            const double sb = block_sum(acc_bot, red);
-            if (threadIdx.x == 0) out[2 * o] = (pass == 0 ? 0.0 : out[2 * o]) + sb;
-            const double st = block_sum(acc_top, red);
-            if (threadIdx.x == 0) out[2 * o + 1] = (pass == 0 ? 0.0 : out[2 * o + 1]) + st;
-        }
+    const int* it = itab + (long long)geom * itab_stride;
+    const int NI = it[0], NS = 2 * nz;
+    extern __shared__ double acc[];  // [NI][64]
+    for (int v = 0; v < NI; ++v) acc[v * 64 + lane] = 0.0;
+    if (kx == 0)
+        tgrad_row<R, QC, true>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 1.0 : 0.0, Qg, Dg,
+                               nzt, it, lpg, QY, acc);
+    else
+        tgrad_row<R, QC, false>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 2.0 : 0.0, Qg,
+                                Dg, nzt, it, lpg, QY, acc);
+    __syncthreads();
+    double* out = partial + ((long long)b * ntiles + tile) * NS;
+    for (int v = 0; v < NI; ++v) {
+        const double sv = wave_sum(acc[v * 64 + lane]);
+        if (lane == 0) out[v] = sv;
     }
 }
 
-// Sum the block partials (fixed order) and apply the stacking chain rule.
-__global__ __launch_bounds__(64) void k_tgrad_finish(const double* __restrict__ partial, int nparts,
-                                                     int nz, double* __restrict__ grad_t)
+// Sum the tile partials of each position (fixed order) and apply the stacking
+// chain rule dL/dt_k = sum_p [k < r_p] dL/dz_p.
+__global__ __launch_bounds__(256) void k_tgrad_finish(const double* __restrict__ partial, int nparts,
+                                                      int nz, const int* __restrict__ itab,
+                                                      int itab_stride, int bpg,
+                                                      double* __restrict__ grad_t)
 {
+    __shared__ double red[4];
+    __shared__ double gp[128];
     const int b = blockIdx.x;
-    extern __shared__ double gi[];  // [2 nz]
-    for (int v = threadIdx.x; v < 2 * nz; v += blockDim.x) {
+    const int* it = itab + (long long)(b / bpg) * itab_stride;
+    const int NI = it[0], NS = 2 * nz;
+    for (int v = 0; v < NI; ++v) {
         double s = 0.0;
-        for (int k = 0; k < nparts; ++k) s += partial[((long long)b * nparts + k) * 2 * nz + v];
-        gi[v] = s;
+        for (int k = threadIdx.x; k < nparts; k += blockDim.x)
+            s += partial[((long long)b * nparts + k) * NS + v];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) gp[v] = s;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nz; k += blockDim.x) {
         double s = 0.0;
-        for (int l = 0; l < nz; ++l) {
-            if (k < l) s += gi[2 * l];
-            if (k <= l) s += gi[2 * l + 1];
-        }
+        for (int p = 0; p < NI; ++p)
+            if (k < (it[itab_layout(nz).info + p] >> 2)) s += gp[p];
         grad_t[(long long)b * nz + k] = s;
     }
 }
 
-hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, long long dgs,
-                        const int* zidx, int g_first, const void* lp, int bpg, int QX, int QY,
-                        double* partial, int nblk, hipStream_t s)
+int tgrad_tiles(int M, int LY)
 {
-    dim3 grid(nblk, nb);
+    return M * ((LY / 2 + 31) / 32);
+}
+
+hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
+                        int nb, const void* Q, long long qgs, const void* D, long long dgs, int nzt,
+                        const int* itab, int itab_stride, int g_first, const void* lp, int bpg,
+                        int QX, int QY, double* partial, hipStream_t s)
+{
+    if (nz < 1 || nz > 64 || nb < 1 || bpg < 1 || nb % bpg || LY < 2 || (LY & (LY - 1)))
+        return hipErrorInvalidValue;
+    (void)QX;  // D and Q rows are addressed through nzt and QY
+    const int ntiles = tgrad_tiles(M, LY);
+    const long long nblk = (long long)((ntiles + 7) / 8) * 8 * nb;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * 64 * 2 * nz;  // >= NI x 64
     if (fp64)
-        hipLaunchKernelGGL(k_tgrad<double>, grid, dim3(256), 0, s, (const cpx<double>*)Mh,
-                           (const cpx<double>*)Gh, nz, M, LY, (const double*)Q, qgs,
-                           (const double*)D, dgs, zidx, g_first, (const double*)lp, bpg, QX, QY, b0,
-                           partial);
+        hipLaunchKernelGGL((k_tgrad<double, 8>), dim3((unsigned)nblk), dim3(64), lds, s,
+                           (const cpx<double>*)Mh, (const cpx<double>*)Gh, nz, M, LY,
+                           (const double*)Q, qgs, (const double*)D, dgs, nzt, itab, itab_stride,
+                           g_first, (const double*)lp, bpg, QY, b0, ntiles, partial);
     else
-        hipLaunchKernelGGL(k_tgrad<float>, grid, dim3(256), 0, s, (const cpx<float>*)Mh,
-                           (const cpx<float>*)Gh, nz, M, LY, (const float*)Q, qgs, (const float*)D,
-                           dgs, zidx, g_first, (const float*)lp, bpg, QX, QY, b0, partial);
+        hipLaunchKernelGGL((k_tgrad<float, 8>), dim3((unsigned)nblk), dim3(64), lds, s,
+                           (const cpx<float>*)Mh, (const cpx<float>*)Gh, nz, M, LY,
+                           (const float*)Q, qgs, (const float*)D, dgs, nzt, itab, itab_stride, g_first,
+                           (const float*)lp, bpg, QY, b0, ntiles, partial);
     return hipGetLastError();
 }
 
-hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, double* grad_t,
-                               hipStream_t s)
+hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const int* itab,
+                               int itab_stride, int bpg, double* grad_t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tgrad_finish, dim3(B), dim3(64), sizeof(double) * 2 * nz, s, partial,
-                       nparts, nz, grad_t);
+    if (nz < 1 || nz > 64 || B < 1 || bpg < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tgrad_finish, dim3(B), dim3(256), 0, s, partial, nparts, nz, itab,
+                       itab_stride, bpg, grad_t);
     return hipGetLastError();
 }
 
