@@ -449,11 +449,13 @@ hfd_status check_equidistant(int nz, int G, const std::vector<double>& t, const 
 }
 
 
-// Distinct z offsets zeta = (interface of the target) - (interface of the
-// source) over all ordered layer pairs, merged when equal to 1e-12 relative,
-// and per geometry the table of k_tgrad: interface positions (top_l and
-// bot_{l+1} merged when they touch), their ranks, the position of every
-// layer's bottom and top, and the D slot of z_p - z_q for every position pair.
+// Distinct offsets |zeta| = |(interface of the target) - (interface of the
+// source)| over all ordered layer pairs, merged when equal to 1e-12 relative
+// (D(-zeta) is D(zeta) with xx, yy, zz, xy negated: those derivatives are odd
+// in zeta, xz and yz even), and per geometry the table of k_tgrad: interface
+// positions (top_l and bot_{l+1} merged when they touch), their ranks, the
+// position of every layer's bottom and top, and for every position pair the
+// D slot of |z_p - z_q| times 2, plus 1 when z_p < z_q.
 void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>& itab,
                         std::vector<int>& count, int& nmax)
 {
@@ -471,7 +473,8 @@ void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>&
         for (int i = 0; i < nz; ++i)
             for (int j = 0; j < nz; ++j) {
                 const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
-                all.insert(all.end(), {ti - bj, bi - bj, ti - tj, bi - tj});
+                all.insert(all.end(), {std::fabs(ti - bj), std::fabs(bi - bj), std::fabs(ti - tj),
+                                       std::fabs(bi - tj)});
             }
         std::vector<double> u = all;
         std::sort(u.begin(), u.end());
@@ -515,7 +518,11 @@ void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>&
         const int NI = (int)pz.size();
         tab[0] = NI;
         for (int a = 0; a < NI; ++a)
-            for (int c = 0; c < NI; ++c) zpq[a * lay.nsp + c] = nearest(pz[a] - pz[c]);
+            for (int c = 0; c < NI; ++c) {
+                const double v = pz[a] - pz[c];
+                const int k = nearest(std::fabs(v));
+                zpq[a * lay.nsp + c] = 2 * k + (v < 0.0 && m[k] != 0.0 ? 1 : 0);
+            }
         per[g] = m;
         count[g] = (int)m.size();
         nmax = std::max(nmax, (int)m.size());

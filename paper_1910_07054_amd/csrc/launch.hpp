@@ -56,9 +56,9 @@ int tgrad_tiles(int M, int LY);
 // Per-geometry interface table of the thickness gradient (ints): [0] NI, the
 // number of interface positions; pinfo[nsp] at `info` (rank r*4 + 1 if the top
 // of layer r-1 is there + 2 if the bottom of layer r is there); pos_bot[nz],
-// pos_top[nz]; zpq[nsp][nsp] at `zpq`, the D slot of z_p - z_q.  nsp = 2nz
-// rounded up to 8 and every row 32-byte aligned, so a chunk of 8 entries is
-// two aligned 16-byte loads; padding entries are slot 0.
+// pos_top[nz]; zpq[nsp][nsp] at `zpq`: 2 x (D slot of |z_p - z_q|) + 1 when
+// z_p < z_q.  nsp = 2nz rounded up to 8 and every row 32-byte aligned, so a
+// chunk of 8 entries is two aligned 16-byte loads; padding entries are slot 0.
 struct ITabLayout {
     int nsp, info, pbot, ptop, zpq, stride;
 };

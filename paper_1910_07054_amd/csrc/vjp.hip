@@ -73,22 +73,26 @@ __device__ inline double gAm(const double g[6], double xx, double yy, double zz,
 
 }  // namespace
 
-// QC = 8 consecutive table entries from a 32-byte aligned address
+// QC (4 or 8) consecutive table entries from a 16 QC-byte aligned address
 template <int QC>
 __device__ inline void load8(const int* __restrict__ src, int (&dst)[QC])
 {
-    static_assert(QC == 8, "interface chunks hold 8 positions");
-    const int4 a = reinterpret_cast<const int4*>(src)[0], b = reinterpret_cast<const int4*>(src)[1];
-    dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
-    dst[4] = b.x; dst[5] = b.y; dst[6] = b.z; dst[7] = b.w;
+    static_assert(QC == 4 || QC == 8, "interface chunks hold 4 or 8 positions");
+#pragma unroll
+    for (int h = 0; h < QC / 4; ++h) {
+        const int4 a = reinterpret_cast<const int4*>(src)[h];
+        dst[4 * h] = a.x; dst[4 * h + 1] = a.y; dst[4 * h + 2] = a.z; dst[4 * h + 3] = a.w;
+    }
 }
 
 // Per-position gradient sums of one wave over its 64 frequencies of row kx
 // (PACKED: the packed column, rows 0 and M from the unpacked pair A, B).
-// Every load of an iteration is issued without a branch in between: the
-// two layers of a position are always read (clamped index, weight 0 when
-// absent) and source slots past NI read the table's padding slot 0 against
-// Mhat = 0.
+// Sources (interface positions, then layers) are taken in chunks of QC held
+// in registers; for each target the loads of the next target are issued
+// before the arithmetic of the current one (software pipelining), and no
+// load sits behind a branch: the two layers of a position are always read
+// (clamped index, weight 0 when absent), source slots past the end read a
+// valid slot against a zero source.
 template <typename R, int QC, bool PACKED>
 __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __restrict__ gb,
                                  long long sst, int nz, int M, int kx, int ky, int kyn, int kq,
@@ -96,6 +100,7 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
                                  const R* __restrict__ Dg, int nzt, const int* __restrict__ it,
                                  const R* __restrict__ lpg, int QY, double* __restrict__ acc)
 {
+    constexpr int NV = PACKED ? 2 : 1;  // raw spectrum values per entry (ky, and LY - ky)
     const int lane = threadIdx.x;
     const int P = nz * (nz + 1) / 2;
     const ITabLayout lay = itab_layout(nz);
@@ -106,48 +111,90 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
     const int* zpq = it + lay.zpq;
     // acc[v][64]: lane-owned partial sums of position v (LDS, fire-and-forget adds)
     auto add_out = [&](int v, double val) { atomicAdd(&acc[v * 64 + lane], val); };
-    for (int ps = 0; ps < (PACKED ? 2 : 1); ++ps) {
+    for (int ps = 0; ps < NV; ++ps) {
         const int row = PACKED ? (ps ? M : 0) : kx;
-        const R* Drow = Dg + (long long)row * nzt * 6 * QY + kq;  // D: [QX][nzt][6][QY]
-        // spectrum (re, im) of component c of layer l at this point
-        auto spec = [&](const cpx<R>* base, int c, int l, double& re, double& im) {
-            const cpx<R> z1 = base[(c * nz + l) * sst + ky];
+        // rows of D ([QX][nzt][6][QY]) and Q ([QX][P][5][QY]) as buffers: the
+        // lane offset is kq, the slot / pair and component offsets are scalar
+        const UniformBuf<R> dbuf(Dg + (long long)row * nzt * 6 * QY, (unsigned)(nzt * 6 * QY * sizeof(R)));
+        const UniformBuf<R> qbuf(Qg + (long long)row * P * 5 * QY, (unsigned)(P * 5 * QY * sizeof(R)));
+        // component c of layer l: raw loads, then (re, im) at this point
+        auto raw = [&](const cpx<R>* base, int c, int l, cpx<R> (&z)[NV]) {
+            z[0] = base[(c * nz + l) * sst + ky];
+            if (PACKED) z[NV - 1] = base[(c * nz + l) * sst + kyn];
+        };
+        auto comb = [&](const cpx<R> (&z)[NV], double& re, double& im) {
             if (!PACKED) {
-                re = z1.x;
-                im = z1.y;
+                re = z[0].x;
+                im = z[0].y;
             } else {
-                const cpx<R> z2 = base[(c * nz + l) * sst + kyn];
+                const cpx<R> z1 = z[0], z2 = z[NV - 1];
                 const double ar = 0.5 * ((double)z1.x + z2.x), ai = 0.5 * ((double)z1.y - z2.y);
                 const double br = 0.5 * ((double)z1.y + z2.y), bi = 0.5 * ((double)z2.x - z1.x);
                 re = ps ? br : ar;
                 im = ps ? bi : ai;
             }
         };
-        // interface pairs, sources in chunks of QC held in registers
+        // ---- interface pairs ------------------------------------------------
+        struct PosLoads {
+            R d[QC][6];
+            cpx<R> g[2][3][NV];
+            int zi[QC];
+        };
         for (int qc = 0; qc < NI; qc += QC) {
             R mh[QC][6];  // Mhat in plan precision
-            int pi[QC];
-            load8(pinfo + qc, pi);
+            {
+                int pi[QC];
+                load8(pinfo + qc, pi);
+                cpx<R> zm[QC][2][3][NV];
 #pragma unroll
-            for (int q = 0; q < QC; ++q) {
-                const bool live = qc + q < NI;
-                const int info = pi[q], rk = info >> 2;
-                const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
-                const double wa = live && (info & 1) ? -1.0 : 0.0;  // top of rk - 1: -M
-                const double wb = live && (info & 2) ? 1.0 : 0.0;   // bottom of rk: +M
+                for (int q = 0; q < QC; ++q) {
+                    const int rk = pi[q] >> 2;
+                    const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double ra, ia, rb, ib;
-                    spec(mb, c, la, ra, ia);
-                    spec(mb, c, lb, rb, ib);
-                    mh[q][2 * c] = (R)(wa * ra + wb * rb);
-                    mh[q][2 * c + 1] = (R)(wa * ia + wb * ib);
+                    for (int c = 0; c < 3; ++c) {
+                        raw(mb, c, la, zm[q][0][c]);
+                        raw(mb, c, lb, zm[q][1][c]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const bool live = qc + q < NI;
+                    const int info = pi[q];
+                    const double wa = live && (info & 1) ? -1.0 : 0.0;  // top of rk - 1: -M
+                    const double wb = live && (info & 2) ? 1.0 : 0.0;   // bottom of rk: +M
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double ra, ia, rb, ib;
+                        comb(zm[q][0][c], ra, ia);
+                        comb(zm[q][1][c], rb, ib);
+                        mh[q][2 * c] = (R)(wa * ra + wb * rb);
+                        mh[q][2 * c + 1] = (R)(wa * ia + wb * ib);
+                    }
                 }
             }
+            auto fetch = [&](int p, PosLoads& f) {
+                const int rk = pinfo[p] >> 2;
+                const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
+                load8(zpq + p * lay.nsp + qc, f.zi);
+#pragma unroll
+                for (int q = 0; q < QC; ++q)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        f.d[q][c] = dbuf.ld(kq, (unsigned)(((f.zi[q] >> 1) * 6 + c) * QY));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    raw(gb, c, la, f.g[0][c]);
+                    raw(gb, c, lb, f.g[1][c]);
+                }
+            };
             double gq[QC];
 #pragma unroll
             for (int q = 0; q < QC; ++q) gq[q] = 0.0;
+            PosLoads nxt;
+            fetch(0, nxt);
             for (int p = 0; p < NI; ++p) {
+                const PosLoads cur = nxt;
+                if (p + 1 < NI) fetch(p + 1, nxt);
                 const int info = pinfo[p], rk = info >> 2;
                 const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
                 // top of rk - 1: +G / t; bottom of rk: -G / t (lp holds 1/t)
@@ -157,19 +204,19 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     double ra, ia, rb, ib;
-                    spec(gb, c, la, ra, ia);
-                    spec(gb, c, lb, rb, ib);
+                    comb(cur.g[0][c], ra, ia);
+                    comb(cur.g[1][c], rb, ib);
                     gh[2 * c] = wa * ra + wb * rb;
                     gh[2 * c + 1] = wa * ia + wb * ib;
                 }
-                int zi[QC];
-                load8(zpq + p * lay.nsp + qc, zi);
                 double ga = 0.0;
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
-                    const R* d = Drow + zi[q] * 6 * QY;
-                    const double pd = gAm(gh, d[0], d[QY], d[2 * QY], sgy * (double)d[3 * QY],
-                                          d[4 * QY], sgy * (double)d[5 * QY], mh[q]);
+                    const R* d = cur.d[q];
+                    // z_p < z_q: D(-zeta) = D(zeta) with xx, yy, zz, xy negated
+                    const double sz = (cur.zi[q] & 1) ? -1.0 : 1.0;
+                    const double pd = gAm(gh, sz * d[0], sz * d[1], sz * d[2], sz * sgy * (double)d[3],
+                                          d[4], sgy * (double)d[5], mh[q]);
                     ga += pd;
                     gq[q] -= pd;
                 }
@@ -179,36 +226,76 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
             for (int q = 0; q < QC; ++q)
                 if (qc + q < NI) add_out(qc + q, gq[q]);
         }
-        // the 1/t_l factor: top_l gets -L_l / t_l, bot_l gets +L_l / t_l; the
-        // stored blocks are t_i T^{ij}
-        for (int l = 0; l < nz; ++l) {
-            const double it_l = lpg[l];  // lp holds 1/t
-            const double w = wgt0 * it_l * it_l;
-            double g6[6];
+        // ---- the 1/t_l factor ----------------------------------------------
+        // top_l gets -L_l / t_l, bot_l gets +L_l / t_l, L_l = sum_j
+        // Re conj(G_l) . T^{lj} M_j; the stored blocks are t_l T^{lj}
+        struct LayerLoads {
+            R a[QC][5];
+            cpx<R> g[3][NV];
+        };
+        for (int jc = 0; jc < nz; jc += QC) {
+            R mj[QC][6];
+            {
+                cpx<R> zm[QC][3][NV];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double re, im;
-                spec(gb, c, l, re, im);
-                g6[2 * c] = w * re;
-                g6[2 * c + 1] = w * im;
-            }
-            double sl = 0.0;
-#pragma unroll 4
-            for (int j = 0; j < nz; ++j) {
-                const int a = l < j ? l : j, bq = l < j ? j : l;
-                const int u = a * nz - a * (a - 1) / 2 + (bq - a);
-                const R* q = Qg + ((long long)row * P + u) * 5 * QY + kq;
-                const double simag = l <= j ? 1.0 : -1.0;
-                const double xx = q[0], yy = q[QY];
-                const double zz = -(xx + yy) + (l == j ? (double)lpg[nz + l] : 0.0);
-                double m6[6];
+                for (int q = 0; q < QC; ++q) {
+                    const int j = jc + q < nz ? jc + q : nz - 1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) spec(mb, c, j, m6[2 * c], m6[2 * c + 1]);
-                sl += gAm(g6, xx, yy, zz, sgy * (double)q[2 * QY], simag * (double)q[3 * QY],
-                          simag * sgy * (double)q[4 * QY], m6);
+                    for (int c = 0; c < 3; ++c) raw(mb, c, j, zm[q][c]);
+                }
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const double w = jc + q < nz ? 1.0 : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double re, im;
+                        comb(zm[q][c], re, im);
+                        mj[q][2 * c] = (R)(w * re);
+                        mj[q][2 * c + 1] = (R)(w * im);
+                    }
+                }
             }
-            add_out(ptop[l], -sl);
-            add_out(pbot[l], sl);
+            auto fetch = [&](int l, LayerLoads& f) {
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const int j = jc + q < nz ? jc + q : nz - 1;
+                    const int a = l < j ? l : j, bq = l < j ? j : l;
+                    const int u = a * nz - a * (a - 1) / 2 + (bq - a);
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) f.a[q][c] = qbuf.ld(kq, (unsigned)((u * 5 + c) * QY));
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) raw(gb, c, l, f.g[c]);
+            };
+            LayerLoads nxt;
+            fetch(0, nxt);
+            for (int l = 0; l < nz; ++l) {
+                const LayerLoads cur = nxt;
+                if (l + 1 < nz) fetch(l + 1, nxt);
+                const double it_l = lpg[l];  // lp holds 1/t
+                const double w = wgt0 * it_l * it_l;
+                const double trace = lpg[nz + l];
+                double g6[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double re, im;
+                    comb(cur.g[c], re, im);
+                    g6[2 * c] = w * re;
+                    g6[2 * c + 1] = w * im;
+                }
+                double sl = 0.0;
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const int j = jc + q;
+                    const double simag = l <= j ? 1.0 : -1.0;
+                    const double xx = cur.a[q][0], yy = cur.a[q][1];
+                    const double zz = -(xx + yy) + (l == j ? trace : 0.0);
+                    sl += gAm(g6, xx, yy, zz, sgy * (double)cur.a[q][2], simag * (double)cur.a[q][3],
+                              simag * sgy * (double)cur.a[q][4], mj[q]);
+                }
+                add_out(ptop[l], -sl);
+                add_out(pbot[l], sl);
+            }
         }
     }
 }
@@ -322,12 +409,12 @@ hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 64 * 2 * nz;  // >= NI x 64
     if (fp64)
-        hipLaunchKernelGGL((k_tgrad<double, 8>), dim3((unsigned)nblk), dim3(64), lds, s,
+        hipLaunchKernelGGL((k_tgrad<double, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<double>*)Mh, (const cpx<double>*)Gh, nz, M, LY,
                            (const double*)Q, qgs, (const double*)D, dgs, nzt, itab, itab_stride,
                            g_first, (const double*)lp, bpg, QY, b0, ntiles, partial);
     else
-        hipLaunchKernelGGL((k_tgrad<float, 8>), dim3((unsigned)nblk), dim3(64), lds, s,
+        hipLaunchKernelGGL((k_tgrad<float, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<float>*)Mh, (const cpx<float>*)Gh, nz, M, LY,
                            (const float*)Q, qgs, (const float*)D, dgs, nzt, itab, itab_stride, g_first,
                            (const float*)lp, bpg, QY, b0, ntiles, partial);
