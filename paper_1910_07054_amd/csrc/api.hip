@@ -108,14 +108,13 @@ struct hfd_plan_s {
     void* Hh = nullptr;
     size_t x1_bytes = 0, mh_bytes = 0;
     // thickness-derivative data
-    void* D = nullptr;          // [G or 1][QX][nzeta_max][6][QY] plan precision
-    long long d_geom_stride = 0;  // elements per geometry
-    int d_geoms = 0;            // geometries D holds (G when stored, else 1)
+    void* D = nullptr;          // [QX][nzeta_max][6][QY] plan precision, one offset table
+    long long d_geom_stride = 0;  // elements of the one table D holds
     int* itab = nullptr;        // [G][itab_stride] interface positions and D slots (k_tgrad)
     int itab_stride = 0;
-    double* zeta_dev = nullptr; // [G][nzeta_max]
+    double* zeta_dev = nullptr; // [tables][nzeta_max]
     int nzeta_max = 0;
-    std::vector<int> nzeta;     // per geometry
+    std::vector<int> nzeta;     // per table (one shared table when stored, else per stack)
     std::vector<double> zeta_host;
     std::vector<int> itab_host;
     bool d_valid = false;       // D holds the current geometry (stored mode)
@@ -456,45 +455,65 @@ hfd_status check_equidistant(int nz, int G, const std::vector<double>& t, const 
 // positions (top_l and bot_{l+1} merged when they touch), their ranks, the
 // position of every layer's bottom and top, and for every position pair the
 // D slot of |z_p - z_q| times 2, plus 1 when z_p < z_q.
-void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>& itab,
+void derivative_offsets(hfd_plan p, bool shared, std::vector<double>& zeta, std::vector<int>& itab,
                         std::vector<int>& count, int& nmax)
 {
     const int nz = p->nz, G = p->G;
     const ITabLayout lay = itab_layout(nz);
     const int stride = lay.stride;
-    std::vector<std::vector<double>> per(G);
     itab.assign((size_t)G * stride, 0);
-    count.assign(G, 0);
-    nmax = 0;
-    for (int g = 0; g < G; ++g) {
-        const double* t = &p->thick[(size_t)g * nz];
-        const double* z = &p->zbot[(size_t)g * nz];
-        std::vector<double> all;
-        for (int i = 0; i < nz; ++i)
-            for (int j = 0; j < nz; ++j) {
-                const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
-                all.insert(all.end(), {std::fabs(ti - bj), std::fabs(bi - bj), std::fabs(ti - tj),
+    auto geo = [&](int g, const double*& t, const double*& z) {
+        t = &p->thick[(size_t)g * nz];
+        z = &p->zbot[(size_t)g * nz];
+    };
+    auto scale_of = [&](int g) {
+        const double *t, *z;
+        geo(g, t, z);
+        double sc = 0.0;
+        for (int l = 0; l < nz; ++l) sc = std::max(sc, std::fabs(z[l]) + t[l]);
+        return sc;
+    };
+    // sorted distinct |offsets| of stacks g0 .. g1-1, values within rounding of
+    // zero snapped to exactly zero (touching interfaces)
+    auto offsets = [&](int g0, int g1) {
+        std::vector<double> u;
+        double sc = 0.0;
+        for (int g = g0; g < g1; ++g) {
+            const double *t, *z;
+            geo(g, t, z);
+            sc = std::max(sc, scale_of(g));
+            for (int i = 0; i < nz; ++i)
+                for (int j = 0; j < nz; ++j) {
+                    const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
+                    u.insert(u.end(), {std::fabs(ti - bj), std::fabs(bi - bj), std::fabs(ti - tj),
                                        std::fabs(bi - tj)});
-            }
-        std::vector<double> u = all;
+                }
+        }
         std::sort(u.begin(), u.end());
         std::vector<double> m;
         for (double v : u) {
             if (!m.empty() && std::fabs(v - m.back()) <= 1e-12 * std::max(1.0, std::fabs(v))) continue;
             m.push_back(v);
         }
-        // snap values within rounding of zero to exactly zero (touching interfaces)
-        double scale = 0.0;
-        for (int l = 0; l < nz; ++l) scale = std::max(scale, std::fabs(z[l]) + t[l]);
-        const double ztol = 1e-12 * std::max(1.0, scale);
         for (double& v : m)
-            if (std::fabs(v) <= ztol) v = 0.0;
+            if (std::fabs(v) <= 1e-12 * std::max(1.0, sc)) v = 0.0;
+        return m;
+    };
+    // one table for every stack (shared) or one per stack
+    std::vector<std::vector<double>> tables;
+    if (shared) tables.push_back(offsets(0, G));
+    else
+        for (int g = 0; g < G; ++g) tables.push_back(offsets(g, g + 1));
+    for (int g = 0; g < G; ++g) {
+        const double *t, *z;
+        geo(g, t, z);
+        const std::vector<double>& m = tables[shared ? 0 : g];
+        const double ztol = 1e-12 * std::max(1.0, scale_of(g));
         auto nearest = [&](double v) {
-            int best = 0;
-            double bd = 1e300;
-            for (int k = 0; k < (int)m.size(); ++k)
-                if (std::fabs(m[k] - v) < bd) { bd = std::fabs(m[k] - v); best = k; }
-            return best;
+            const auto it = std::lower_bound(m.begin(), m.end(), v);
+            int k = (int)(it - m.begin());
+            if (k == (int)m.size() || (k > 0 && std::fabs(m[k - 1] - v) <= std::fabs(m[k] - v))) --k;
+            return k;
         };
         // interface positions bottom to top
         int* tab = &itab[(size_t)g * stride];
@@ -523,13 +542,17 @@ void derivative_offsets(hfd_plan p, std::vector<double>& zeta, std::vector<int>&
                 const int k = nearest(std::fabs(v));
                 zpq[a * lay.nsp + c] = 2 * k + (v < 0.0 && m[k] != 0.0 ? 1 : 0);
             }
-        per[g] = m;
-        count[g] = (int)m.size();
-        nmax = std::max(nmax, (int)m.size());
     }
-    zeta.assign((size_t)G * nmax, 0.0);
-    for (int g = 0; g < G; ++g)
-        for (int k = 0; k < count[g]; ++k) zeta[(size_t)g * nmax + k] = per[g][k];
+    const int T = (int)tables.size();
+    count.assign(T, 0);
+    nmax = 0;
+    for (int k = 0; k < T; ++k) {
+        count[k] = (int)tables[k].size();
+        nmax = std::max(nmax, count[k]);
+    }
+    zeta.assign((size_t)T * nmax, 0.0);
+    for (int k = 0; k < T; ++k)
+        for (int i = 0; i < count[k]; ++i) zeta[(size_t)k * nmax + i] = tables[k][i];
 }
 
 // Allocate (or re-allocate) the derivative buffers and upload the offsets.
@@ -538,20 +561,19 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     std::vector<double> zeta;
     std::vector<int> itab, count;
     int nmax = 0;
-    derivative_offsets(p, zeta, itab, count, nmax);
-    const bool store = p->flags & HFD_STORE_DTENSOR;
-    const int dgeoms = store ? p->G : 1;
+    // stored: one table shared by all stacks; recomputed: one table per stack,
+    // built into the same buffer before that stack's reduction
+    derivative_offsets(p, (p->flags & HFD_STORE_DTENSOR) != 0, zeta, itab, count, nmax);
     const long long per_geom = (long long)nmax * 6 * p->QX * p->QY;
     if (nmax > p->nzeta_max || !p->D) {
         if (p->D) (void)hipFree(p->D);
         if (p->zeta_dev) (void)hipFree(p->zeta_dev);
         p->D = nullptr;
         p->zeta_dev = nullptr;
-        HFD_TRY(dev_alloc(&p->D, (size_t)per_geom * dgeoms * p->rsz, "derivative tensor"));
+        HFD_TRY(dev_alloc(&p->D, (size_t)per_geom * p->rsz, "derivative tensor"));
         HFD_TRY(dev_alloc(&p->zeta_dev, sizeof(double) * zeta.size(), "derivative offsets"));
         p->nzeta_max = nmax;
         p->d_geom_stride = per_geom;
-        p->d_geoms = dgeoms;
     }
     if (!p->itab) HFD_TRY(dev_alloc(&p->itab, sizeof(int) * itab.size(), "interface table"));
     p->itab_stride = itab_layout(p->nz).stride;
@@ -572,10 +594,14 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
         HFD_HIP(hipMemcpyAsync(p->dscale, sc.data(), sizeof(double) * chunk, hipMemcpyHostToDevice, s));
         p->dchunk = chunk;
     }
-    p->zeta_host = zeta;
+    // offsets of table k at k * nzeta_max (the allocated stride, which stays
+    // larger than nmax when a new geometry has fewer distinct offsets)
+    p->zeta_host.assign(count.size() * (size_t)p->nzeta_max, 0.0);
+    for (size_t k = 0; k < count.size(); ++k)
+        for (int i = 0; i < count[k]; ++i) p->zeta_host[k * p->nzeta_max + i] = zeta[k * nmax + i];
     p->itab_host = itab;
     p->nzeta = count;
-    HFD_HIP(hipMemcpyAsync(p->zeta_dev, p->zeta_host.data(), sizeof(double) * zeta.size(),
+    HFD_HIP(hipMemcpyAsync(p->zeta_dev, p->zeta_host.data(), sizeof(double) * p->zeta_host.size(),
                            hipMemcpyHostToDevice, s));
     HFD_HIP(hipMemcpyAsync(p->itab, p->itab_host.data(), sizeof(int) * itab.size(),
                            hipMemcpyHostToDevice, s));
@@ -593,13 +619,14 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     return HFD_OK;
 }
 
-// D(zeta) of geometry g into slot `slot` of p->D: FP64 lattice of the
-// lateral-stencilled z-derivative, FP64 2D FFT, packed to plan precision.
-hfd_status compute_derivatives(hfd_plan p, int g, int slot, hipStream_t s)
+// D(|zeta|) of offset table k (the shared table when stored, else stack k)
+// into p->D: FP64 lattice of the lateral-stencilled z-derivative, FP64 2D FFT,
+// packed to plan precision.
+hfd_status compute_derivatives(hfd_plan p, int g, hipStream_t s)
 {
     const long long plane = (long long)p->Lx * p->Ly;
     const int nzt = p->nzeta[g];
-    char* dst = (char*)p->D + (size_t)slot * p->d_geom_stride * p->rsz;
+    char* dst = (char*)p->D;
     for (int z0 = 0; z0 < nzt; z0 += p->dchunk) {
         const int nc = std::min(p->dchunk, nzt - z0);
         HFD_HIP(launch_zero64((double*)p->dW, (long long)nc * 6 * plane, s));
@@ -828,7 +855,7 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         st = setup_derivatives(p, s);
         if (st) break;
         if (flags & HFD_STORE_DTENSOR) {
-            for (int g = 0; g < n_geom && st == HFD_OK; ++g) st = compute_derivatives(p, g, g, s);
+            st = compute_derivatives(p, 0, s);
             if (st == HFD_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(HFD_EHIP, "sync failed");
             p->d_valid = (st == HFD_OK);
         }
@@ -861,7 +888,7 @@ hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* 
     HFD_TRY(build_tensor(p, s));
     HFD_TRY(setup_derivatives(p, s));
     if (p->flags & HFD_STORE_DTENSOR) {
-        for (int g = 0; g < p->G; ++g) HFD_TRY(compute_derivatives(p, g, g, s));
+        HFD_TRY(compute_derivatives(p, 0, s));
         HFD_HIP(hipStreamSynchronize(s));
         p->d_valid = true;
     }
@@ -905,15 +932,15 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     const int bpg = batch / p->G;
     if (p->d_valid) {
         HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
-                             p->D, p->d_geom_stride, p->nzeta_max, p->itab, p->itab_stride, 0, p->lp,
+                             p->D, 0, p->nzeta_max, p->itab, p->itab_stride, 0, p->lp,
                              bpg, p->QX,
                              p->QY, p->partial, s));
     } else {
         // recompute the derivative tensor of one stack at a time
         for (int g = 0; g < p->G; ++g) {
-            HFD_TRY(compute_derivatives(p, g, 0, s));
+            HFD_TRY(compute_derivatives(p, g, s));
             HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g * bpg, bpg, p->Q,
-                                 p->q_geom_stride, p->D, p->d_geom_stride, p->nzeta_max, p->itab,
+                                 p->q_geom_stride, p->D, 0, p->nzeta_max, p->itab,
                                  p->itab_stride,
                                  g, p->lp, bpg, p->QX, p->QY, p->partial, s));
         }

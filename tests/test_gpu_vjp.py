@@ -104,3 +104,51 @@ def test_thickness_gradient_matches_fp64_finite_differences():
         fd = (vals[0] - vals[1]) / (2 * eps)
         assert gt[0, k] == pytest.approx(fd, rel=1e-6, abs=1e-9)
     plan.destroy()
+
+
+@pytest.mark.parametrize("nz, gaps", [(1, None), (20, "mixed")], ids=["one_layer", "twenty_layers_gaps"])
+def test_thickness_gradient_interface_counts(nz, gaps):
+    """One layer (two interface positions) and 20 layers where some layers
+    touch and others have gaps (32 positions: several source chunks and the
+    widest per-position accumulator), FP64 against the oracle."""
+    rng = np.random.default_rng(40 + nz)
+    nx, ny = 7, 6
+    t = rng.uniform(0.4, 2.0, nz)
+    if gaps is None:
+        zb = W.stack_bottoms(t, np.zeros(nz - 1))
+    else:
+        gv = np.where(np.arange(nz - 1) % 5 == 2, 0.0, rng.uniform(0.05, 0.6, nz - 1))
+        gv[::4] = 0.0
+        zb = W.stack_bottoms(t, gv)
+    m = W.random_unit(rng, (nz, ny, nx))[None]
+    g = rng.standard_normal(m.shape)
+    plan = hfd.Plan(nx, ny, 1.5, 2.0, t, zb, batch_max=1, flags=hfd.HFD_FP64)
+    _, gt = _vjp(plan, m, g, want_m=False)
+    ref = oracle.thickness_grad(nx, ny, 1.5, 2.0, zb, t, m[0], g[0])
+    assert np.abs(gt[0] - ref).max() < 1e-10 * np.abs(ref).max(), (gt[0], ref)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("store", [False, True], ids=["recompute", "stored"])
+def test_thickness_gradient_after_reset_to_fewer_offsets(store):
+    """Two stacks; after set_thickness to stacks with fewer distinct interface
+    offsets (equal layers) the offset tables keep their allocated stride, and
+    every stack's gradient still matches the oracle (FP64)."""
+    rng = np.random.default_rng(77)
+    nx, ny, nz, G = 6, 5, 3, 2
+    flags = hfd.HFD_FP64 | (hfd.HFD_STORE_DTENSOR if store else 0)
+    t1 = rng.uniform(0.5, 2.5, (G, nz))
+    z1 = np.stack([W.stack_bottoms(t1[g], [0.2, 0.45]) for g in range(G)])
+    plan = hfd.Plan(nx, ny, 1.0, 1.5, t1, z1, batch_max=G, flags=flags)
+    t2 = np.array([[1.0, 1.0, 1.0], [0.7, 0.7, 0.7]])
+    z2 = np.stack([W.stack_bottoms(t2[g], [0.0, 0.0]) for g in range(G)])
+    m = np.stack([W.random_unit(rng, (nz, ny, nx)) for _ in range(G)])
+    g = rng.standard_normal(m.shape)
+    for t, z in ((t1, z1), (t2, z2)):
+        if t is t2:
+            plan.set_thickness(t, z)
+        _, gt = _vjp(plan, m, g, want_m=False)
+        for b in range(G):
+            ref = oracle.thickness_grad(nx, ny, 1.0, 1.5, z[b], t[b], m[b], g[b])
+            assert np.abs(gt[b] - ref).max() < 1e-10 * np.abs(ref).max(), (store, b, gt[b], ref)
+    plan.destroy()
