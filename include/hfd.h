@@ -66,7 +66,10 @@ enum {
                                    y-FFT as separate kernels) even where the fused
                                    y-pass fits in LDS                                  */
     HFD_STORE_DTENSOR = 8,      /* keep the thickness-derivative tensors resident
-                                   between hfd_demag_vjp calls (default: recompute)   */
+                                   between hfd_demag_vjp calls: one table over the
+                                   distinct |interface offsets| of all stacks, built
+                                   by setup / hfd_set_thickness (default: rebuilt
+                                   per stack inside every call)                       */
     HFD_MIX_BATCHED_FP32 = 16,  /* five-pass path with the batched (16 states per
                                    block) FP32 VALU mixing, the FP32 twin of
                                    HFD_MIX_SPLIT_BF16                                 */
