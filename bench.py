@@ -3,9 +3,11 @@
 One step = one full field evaluation h = -N * m (x-pass R2C, y-pass with the
 explicit z-mixing, inverse x-pass) of the 256 x 256 x 8 MRAM-like stack
 (2.5 nm cells, FP32 field, tensor set up in FP64 beforehand), inputs resident
-in HBM.  Steps are replayed from a HIP graph.  Prints one JSON line.
+in HBM.  Steps are replayed from a HIP graph that holds G complete evaluations
+(G: the largest divisor of K up to 10, or --graph-evals), so K steps are K / G
+replays.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph] [--graph-evals G]
 """
 from __future__ import annotations
 
@@ -32,6 +34,9 @@ def parse():
     ap.add_argument("--workload", default="M0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--graph-evals", type=int, default=0,
+                    help="evaluations captured per HIP graph (0: the largest divisor of --steps "
+                         "up to 10); each replay runs that many complete evaluations")
     ap.add_argument("--split", action="store_true", help="force the five-pass path")
     ap.add_argument("--compare", action="store_true",
                     help="also time every mixing path (and 64 single-state calls) on the workload, "
@@ -311,11 +316,18 @@ def main():
             plan.field(m, out=h, stream=stream)
     torch.cuda.synchronize()
 
+    # G evaluations per graph (a time-stepping code captures its inner loop the
+    # same way); K steps = K / G replays, every step a complete evaluation
     graph = None
+    G = 1
     if not args.no_graph:
+        G = args.graph_evals or max(d for d in range(1, 11) if args.steps % d == 0)
+        if args.steps % G:
+            raise SystemExit(f"--steps {args.steps} is not a multiple of --graph-evals {G}")
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=stream):
-            plan.field(m, out=h, stream=stream)
+            for _ in range(G):
+                plan.field(m, out=h, stream=stream)
         for _ in range(3):
             graph.replay()
         torch.cuda.synchronize()
@@ -323,10 +335,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            if graph is not None:
+        if graph is not None:
+            for _ in range(args.steps // G):
                 graph.replay()
-            else:
+        else:
+            for _ in range(args.steps):
                 plan.field(m, out=h, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -374,7 +387,8 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.nx}x{wl.ny} cells of {wl.dx} nm, {wl.nz} layers "
                                f"(MRAM-like stack, seed {wl.seed}), batch {B}, FP32 field / FP64 tensor",
                    "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "batch": B, "Lx": inf.Lx, "Ly": inf.Ly,
-                   "path": "fused" if inf.fused else "split", "graph": graph is not None},
+                   "path": "fused" if inf.fused else "split", "graph": graph is not None,
+                   "evals_per_graph": G if graph is not None else 0},
         "cell_updates_per_s": evals_per_s * wl.nx * wl.ny * wl.nz,
         "alg_GBps": alg_bytes / (elapsed / args.steps) / 1e9,
         "alg_bytes_per_eval": alg_bytes,
