@@ -109,7 +109,6 @@ struct hfd_plan_s {
     size_t x1_bytes = 0, mh_bytes = 0;
     // thickness-derivative data
     void* D = nullptr;          // [QX][nzeta_max][6][QY] plan precision, one offset table
-    long long d_geom_stride = 0;  // elements of the one table D holds
     int* itab = nullptr;        // [G][itab_stride] interface positions and D slots (k_tgrad)
     int itab_stride = 0;
     double* zeta_dev = nullptr; // [tables][nzeta_max]
@@ -564,16 +563,15 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     // stored: one table shared by all stacks; recomputed: one table per stack,
     // built into the same buffer before that stack's reduction
     derivative_offsets(p, (p->flags & HFD_STORE_DTENSOR) != 0, zeta, itab, count, nmax);
-    const long long per_geom = (long long)nmax * 6 * p->QX * p->QY;
+    const long long per_table = (long long)nmax * 6 * p->QX * p->QY;
     if (nmax > p->nzeta_max || !p->D) {
         if (p->D) (void)hipFree(p->D);
         if (p->zeta_dev) (void)hipFree(p->zeta_dev);
         p->D = nullptr;
         p->zeta_dev = nullptr;
-        HFD_TRY(dev_alloc(&p->D, (size_t)per_geom * p->rsz, "derivative tensor"));
+        HFD_TRY(dev_alloc(&p->D, (size_t)per_table * p->rsz, "derivative tensor"));
         HFD_TRY(dev_alloc(&p->zeta_dev, sizeof(double) * zeta.size(), "derivative offsets"));
         p->nzeta_max = nmax;
-        p->d_geom_stride = per_geom;
     }
     if (!p->itab) HFD_TRY(dev_alloc(&p->itab, sizeof(int) * itab.size(), "interface table"));
     p->itab_stride = itab_layout(p->nz).stride;
@@ -932,17 +930,15 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     const int bpg = batch / p->G;
     if (p->d_valid) {
         HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
-                             p->D, 0, p->nzeta_max, p->itab, p->itab_stride, 0, p->lp,
-                             bpg, p->QX,
-                             p->QY, p->partial, s));
+                             p->D, p->nzeta_max, p->itab, p->itab_stride, p->lp, bpg, p->QX, p->QY,
+                             p->partial, s));
     } else {
         // recompute the derivative tensor of one stack at a time
         for (int g = 0; g < p->G; ++g) {
             HFD_TRY(compute_derivatives(p, g, s));
             HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g * bpg, bpg, p->Q,
-                                 p->q_geom_stride, p->D, 0, p->nzeta_max, p->itab,
-                                 p->itab_stride,
-                                 g, p->lp, bpg, p->QX, p->QY, p->partial, s));
+                                 p->q_geom_stride, p->D, p->nzeta_max, p->itab, p->itab_stride,
+                                 p->lp, bpg, p->QX, p->QY, p->partial, s));
         }
     }
     HFD_HIP(launch_tgrad_finish(p->partial, p->ntiles, batch, p->nz, p->itab, p->itab_stride, bpg,

@@ -74,8 +74,8 @@ __host__ __device__ inline ITabLayout itab_layout(int nz)
     return t;
 }
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, long long dgs, int nzt,
-                        const int* itab, int itab_stride, int g_first, const void* lp, int bpg,
+                        int nb, const void* Q, long long qgs, const void* D, int nzt,
+                        const int* itab, int itab_stride, const void* lp, int bpg,
                         int QX, int QY, double* partial, hipStream_t s);
 hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const int* itab,
                                int itab_stride, int bpg, double* grad_t, hipStream_t s);

@@ -314,9 +314,9 @@ template <typename R, int QC>
 __global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
                                               const cpx<R>* __restrict__ Gh, int nz, int M, int LY,
                                               const R* __restrict__ Q, long long qgs,
-                                              const R* __restrict__ D, long long dgs, int nzt,
+                                              const R* __restrict__ D, int nzt,
                                               const int* __restrict__ itab, int itab_stride,
-                                              int g_first, const R* __restrict__ lp, int bpg,
+                                              const R* __restrict__ lp, int bpg,
                                               int QY, int b0, int ntiles,
                                               double* __restrict__ partial)
 {
@@ -343,18 +343,17 @@ __global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;
     const cpx<R>* gb = Gh + ((long long)b * S * M + kx) * LY;
     const R* Qg = Q + (long long)geom * qgs;
-    const R* Dg = D + (long long)(geom - g_first) * dgs;
     const R* lpg = lp + (long long)geom * 2 * nz;
     const int* it = itab + (long long)geom * itab_stride;
     const int NI = it[0], NS = 2 * nz;
     extern __shared__ double acc[];  // [NI][64]
     for (int v = 0; v < NI; ++v) acc[v * 64 + lane] = 0.0;
     if (kx == 0)
-        tgrad_row<R, QC, true>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 1.0 : 0.0, Qg, Dg,
+        tgrad_row<R, QC, true>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 1.0 : 0.0, Qg, D,
                                nzt, it, lpg, QY, acc);
     else
         tgrad_row<R, QC, false>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 2.0 : 0.0, Qg,
-                                Dg, nzt, it, lpg, QY, acc);
+                                D, nzt, it, lpg, QY, acc);
     __syncthreads();
     double* out = partial + ((long long)b * ntiles + tile) * NS;
     for (int v = 0; v < NI; ++v) {
@@ -397,8 +396,8 @@ int tgrad_tiles(int M, int LY)
 }
 
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, long long dgs, int nzt,
-                        const int* itab, int itab_stride, int g_first, const void* lp, int bpg,
+                        int nb, const void* Q, long long qgs, const void* D, int nzt,
+                        const int* itab, int itab_stride, const void* lp, int bpg,
                         int QX, int QY, double* partial, hipStream_t s)
 {
     if (nz < 1 || nz > 64 || nb < 1 || bpg < 1 || nb % bpg || LY < 2 || (LY & (LY - 1)))
@@ -411,12 +410,12 @@ hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M
     if (fp64)
         hipLaunchKernelGGL((k_tgrad<double, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<double>*)Mh, (const cpx<double>*)Gh, nz, M, LY,
-                           (const double*)Q, qgs, (const double*)D, dgs, nzt, itab, itab_stride,
-                           g_first, (const double*)lp, bpg, QY, b0, ntiles, partial);
+                           (const double*)Q, qgs, (const double*)D, nzt, itab, itab_stride,
+                           (const double*)lp, bpg, QY, b0, ntiles, partial);
     else
         hipLaunchKernelGGL((k_tgrad<float, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<float>*)Mh, (const cpx<float>*)Gh, nz, M, LY,
-                           (const float*)Q, qgs, (const float*)D, dgs, nzt, itab, itab_stride, g_first,
+                           (const float*)Q, qgs, (const float*)D, nzt, itab, itab_stride,
                            (const float*)lp, bpg, QY, b0, ntiles, partial);
     return hipGetLastError();
 }
