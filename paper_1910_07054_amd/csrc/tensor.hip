@@ -21,11 +21,12 @@ hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx,
 hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
                                int Ly, double dx, double dy, hipStream_t s)
 {
-    const long long n = (long long)nx * ny * nzeta;
-    const long long nb = (n + 127) / 128;
-    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dtensor_real, dim3((unsigned)nb), dim3(128), 0, s, W, zeta, nzeta, nx, ny,
-                       Lx, Ly, dx, dy);
+    if (nzeta <= 0) return hipSuccess;
+    if (nzeta > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((nx + kDTile - 1) / kDTile), (unsigned)((ny + kDTile - 1) / kDTile),
+                    (unsigned)nzeta);
+    hipLaunchKernelGGL(k_dtensor_real, grid, dim3(kDTile * kDTile), 0, s, W, zeta, nx, ny, Lx, Ly,
+                       dx, dy);
     return hipGetLastError();
 }
 

@@ -338,25 +338,39 @@ __global__ __launch_bounds__(128) void k_tensor_real(double* __restrict__ W,
 // Lateral-stencilled z-derivative of Phi at height zeta (one per distinct
 // interface difference):  d(p, q) = -1/(4 pi dx dy) sum_{a,b} s_a s_b
 // dPhi_kl/dz(p dx + a, q dy + b, zeta), written like mode 0 above.
-__global__ __launch_bounds__(128) void k_dtensor_real(double* __restrict__ W,
-                                                      const double* __restrict__ zeta, int nzeta,
-                                                      int nx, int ny, int Lx, int Ly, double dx,
-                                                      double dy)
+// The stencil points of neighbouring lattice entries are the lattice points
+// themselves, so a block evaluates dPhi/dz once on its tile of 16 x 16
+// entries plus a one-point halo (18 x 18 points, LDS) and applies the 3 x 3
+// stencil from there: 1.3 evaluations per entry and component instead of 9.
+constexpr int kDTile = 16;
+__global__ __launch_bounds__(kDTile * kDTile) void k_dtensor_real(double* __restrict__ W,
+                                                                  const double* __restrict__ zeta,
+                                                                  int nx, int ny, int Lx, int Ly,
+                                                                  double dx, double dy)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)nx * ny;
-    if (idx >= per * nzeta) return;
-    const int u = (int)(idx / per);
-    const int q = (int)((idx / nx) % ny), p = (int)(idx % nx);
+    constexpr int E = kDTile + 2;  // tile with halo
+    __shared__ double F[6][E][E];
+    const int u = blockIdx.z;
+    const int p0 = blockIdx.x * kDTile, q0 = blockIdx.y * kDTile;
     const double zt = zeta[u];
-    const double X = p * dx, Y = q * dy;
-    const double ox[3] = {dx, 0.0, -dx}, oy[3] = {dy, 0.0, -dy}, w3[3] = {1.0, -2.0, 1.0};
+    for (int k = threadIdx.x; k < E * E; k += blockDim.x) {
+        const int ey = k / E, ex = k - ey * E;
+        const double X = (double)(p0 + ex - 1) * dx, Y = (double)(q0 + ey - 1) * dy;
+        for (int c = 0; c < 6; ++c) F[c][ey][ex] = dphi_dz_c(c, X, Y, zt);
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kDTile, ty = threadIdx.x / kDTile;
+    const int p = p0 + tx, q = q0 + ty;
+    if (p >= nx || q >= ny) return;
+    // offsets {+d, 0, -d} with weights {1, -2, 1}, as in newell_entry
+    const int oi[3] = {1, 0, -1};
+    const double w3[3] = {1.0, -2.0, 1.0};
     const double pref = -1.0 / (4.0 * M_PI * dx * dy);
     double N[6];
     for (int c = 0; c < 6; ++c) {
         double acc = 0.0;
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) acc += w3[a] * w3[b] * dphi_dz_c(c, X + ox[a], Y + oy[b], zt);
+            for (int b = 0; b < 3; ++b) acc += w3[a] * w3[b] * F[c][ty + 1 + oi[b]][tx + 1 + oi[a]];
         N[c] = pref * acc;
     }
     if (p == 0) { N[3] = 0.0; N[4] = 0.0; }
