@@ -135,7 +135,9 @@ hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, voi
  * Either output may be NULL.  The transpose uses reciprocity:
  * (dh/dm)^T = T (dh/dm) T^{-1}, T = diag(t_l).  The thickness derivative uses
  * the derivatives of the Newell kernels with respect to the z offset,
- * evaluated in FP64 and transformed like the tensor.
+ * evaluated in FP64 and transformed like the tensor.  grad_thickness returns
+ * HFD_ENOTSUP on equidistant plans and when one kx row of the derivative
+ * table (distinct interface offsets x 6 x (Ly/2+1) values) exceeds 2 GiB.
  */
 hfd_status hfd_demag_vjp(hfd_plan plan, const void *m, const void *grad_h, void *grad_m,
                          double *grad_thickness, int batch, void *stream);

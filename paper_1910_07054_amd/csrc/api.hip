@@ -909,6 +909,10 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     if (!grad_m && !grad_thickness) return fail(HFD_EINVAL, "grad_m and grad_thickness are both NULL");
     if (p->eq3d && grad_thickness)
         return fail(HFD_ENOTSUP, "thickness gradients need the non-equidistant plan (no HFD_EQUIDISTANT)");
+    if (grad_thickness && (long long)p->nzeta_max * 6 * p->QY * (long long)p->rsz >= (1LL << 31))
+        return fail(HFD_ENOTSUP, "one kx row of the thickness-derivative table exceeds 2 GiB (" +
+                                     std::to_string(p->nzeta_max) + " offsets): use fewer stacks per "
+                                     "plan or leave out HFD_STORE_DTENSOR");
     if (grad_m) HFD_TRY(check_field_args(p, grad_h, grad_m, batch, "grad_h", "grad_m"));
     if (grad_thickness) {
         HFD_TRY(check_field_args(p, m, grad_h, batch, "m", "grad_h"));

@@ -25,7 +25,9 @@
 // kx in [1, M) once (weight 2, the mirror -kx is the complex conjugate) and
 // the packed column 0 carries kx = 0 and kx = Lx/2 (weight 1 each).
 // Position p has rank r_p (r = l for bot_l, l + 1 for top_l) and
-// dz_p/dt_k = [k < r_p].
+// dz_p/dt_k = [k < r_p].  D is stored for |zeta| only: dPsi/dz is odd in zeta
+// for xx, yy, zz, xy and even for xz, yz, so D(-zeta) is D(zeta) with the
+// first four negated (the table entry of a pair carries the sign).
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -73,9 +75,9 @@ __device__ inline double gAm(const double g[6], double xx, double yy, double zz,
 
 }  // namespace
 
-// QC (4 or 8) consecutive table entries from a 16 QC-byte aligned address
+// QC (4 or 8) consecutive table entries from a 4 QC-byte aligned address
 template <int QC>
-__device__ inline void load8(const int* __restrict__ src, int (&dst)[QC])
+__device__ inline void load_chunk(const int* __restrict__ src, int (&dst)[QC])
 {
     static_assert(QC == 4 || QC == 8, "interface chunks hold 4 or 8 positions");
 #pragma unroll
@@ -144,7 +146,7 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
             R mh[QC][6];  // Mhat in plan precision
             {
                 int pi[QC];
-                load8(pinfo + qc, pi);
+                load_chunk(pinfo + qc, pi);
                 cpx<R> zm[QC][2][3][NV];
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
@@ -175,7 +177,7 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
             auto fetch = [&](int p, PosLoads& f) {
                 const int rk = pinfo[p] >> 2;
                 const int la = rk > 0 ? rk - 1 : 0, lb = rk < nz ? rk : nz - 1;
-                load8(zpq + p * lay.nsp + qc, f.zi);
+                load_chunk(zpq + p * lay.nsp + qc, f.zi);
 #pragma unroll
                 for (int q = 0; q < QC; ++q)
 #pragma unroll
@@ -403,6 +405,11 @@ hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M
     if (nz < 1 || nz > 64 || nb < 1 || bpg < 1 || nb % bpg || LY < 2 || (LY & (LY - 1)))
         return hipErrorInvalidValue;
     (void)QX;  // D and Q rows are addressed through nzt and QY
+    // one row of D or Q is a buffer with 32-bit byte offsets
+    const long long rsz = fp64 ? 8 : 4;
+    if ((long long)nzt * 6 * QY * rsz >= (1LL << 31) ||
+        (long long)nz * (nz + 1) / 2 * 5 * QY * rsz >= (1LL << 31))
+        return hipErrorInvalidValue;
     const int ntiles = tgrad_tiles(M, LY);
     const long long nblk = (long long)((ntiles + 7) / 8) * 8 * nb;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
