@@ -52,6 +52,18 @@ def parse():
     return ap.parse_args()
 
 
+def graph_evals(steps: int, requested: int = 0) -> int:
+    """Evaluations captured per HIP graph: `requested`, or the largest divisor
+    of `steps` up to 10, so that `steps` evaluations are a whole number of
+    replays."""
+    if steps < 1:
+        raise SystemExit("--steps must be >= 1")
+    G = requested or max(d for d in range(1, 11) if steps % d == 0)
+    if G < 1 or steps % G:
+        raise SystemExit(f"--steps {steps} is not a multiple of --graph-evals {G}")
+    return G
+
+
 def algorithmic_bytes(nx, ny, nz, B, Lx, Ly):
     """m in + h out (FP32) + the unique-pair Fourier tensor (5 FP32 components on
     the (Lx/2+1) x (Ly/2+1) quadrant) read once."""
@@ -321,9 +333,7 @@ def main():
     graph = None
     G = 1
     if not args.no_graph:
-        G = args.graph_evals or max(d for d in range(1, 11) if args.steps % d == 0)
-        if args.steps % G:
-            raise SystemExit(f"--steps {args.steps} is not a multiple of --graph-evals {G}")
+        G = graph_evals(args.steps, args.graph_evals)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=stream):
             for _ in range(G):
