@@ -152,3 +152,21 @@ def test_thickness_gradient_after_reset_to_fewer_offsets(store):
             ref = oracle.thickness_grad(nx, ny, 1.0, 1.5, z[b], t[b], m[b], g[b])
             assert np.abs(gt[b] - ref).max() < 1e-10 * np.abs(ref).max(), (store, b, gt[b], ref)
     plan.destroy()
+
+
+@pytest.mark.parametrize("nx, ny", [(1, 1), (1, 9), (40, 1)], ids=["1x1", "1x9", "40x1"])
+def test_thickness_gradient_degenerate_lateral_shapes(nx, ny):
+    """One cell, one column, one row (8-point padded axes, waves with lanes past
+    the ky range, a single kx column besides the packed one), FP64 against the
+    oracle, touching and gapped layers."""
+    rng = np.random.default_rng(90 + nx + ny)
+    nz = 3
+    t = rng.uniform(0.5, 2.0, nz)
+    zb = W.stack_bottoms(t, [0.0, 0.4])
+    m = W.random_unit(rng, (nz, ny, nx))[None]
+    g = rng.standard_normal(m.shape)
+    plan = hfd.Plan(nx, ny, 1.0, 2.0, t, zb, batch_max=1, flags=hfd.HFD_FP64)
+    _, gt = _vjp(plan, m, g, want_m=False)
+    ref = oracle.thickness_grad(nx, ny, 1.0, 2.0, zb, t, m[0], g[0])
+    assert np.abs(gt[0] - ref).max() < 1e-10 * np.abs(ref).max(), (gt[0], ref)
+    plan.destroy()
