@@ -627,7 +627,7 @@ hfd_status compute_derivatives(hfd_plan p, int g, hipStream_t s)
     char* dst = (char*)p->D;
     for (int z0 = 0; z0 < nzt; z0 += p->dchunk) {
         const int nc = std::min(p->dchunk, nzt - z0);
-        HFD_HIP(launch_zero64((double*)p->dW, (long long)nc * 6 * plane, s));
+        HFD_HIP(launch_zero_gaps((double*)p->dW, (long long)nc * 6, p->nx, p->ny, p->Lx, p->Ly, s));
         HFD_HIP(launch_dtensor_real(p->dW, p->zeta_dev + (size_t)g * p->nzeta_max + z0, nc, p->nx,
                                     p->ny, p->Lx, p->Ly, p->dx, p->dy, s));
         HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));

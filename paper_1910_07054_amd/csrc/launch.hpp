@@ -88,6 +88,8 @@ hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx,
                               int Ly, double dx, double dy, int mode, hipStream_t s);
 // zero n doubles (a kernel, so that graph captures hold no memset node)
 hipError_t launch_zero64(double* p, long long n, hipStream_t s);
+// zero what k_dtensor_real leaves untouched in nplanes padded Lx x Ly planes
+hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx, int Ly, hipStream_t s);
 hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
                                int Ly, double dx, double dy, hipStream_t s);
 // comps 5: field tensor, written at pairs pair0.. of a [QX][pair_total][5][QY] array;

@@ -48,6 +48,41 @@ hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scal
     return hipGetLastError();
 }
 
+// Zero the entries of nplanes Lx x Ly planes that the lattice kernels leave
+// untouched: columns x in [nx, Lx - nx] and rows y in [ny, Ly - ny] (the images
+// of the nx x ny quadrant cover every other entry).
+__global__ __launch_bounds__(256) void k_zero_gaps(double* __restrict__ W, long long nplanes, int nx,
+                                                  int ny, int Lx, int Ly)
+{
+    const int gx = Lx - 2 * nx + 1, gy = Ly - 2 * ny + 1;
+    const long long per = (long long)gx * Ly + (long long)gy * Lx;
+    const long long n = per * nplanes;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const long long pl = i / per, r = i - pl * per;
+        int x, y;
+        if (r < (long long)gx * Ly) {
+            x = nx + (int)(r % gx);
+            y = (int)(r / gx);
+        } else {
+            const long long r2 = r - (long long)gx * Ly;
+            x = (int)(r2 % Lx);
+            y = ny + (int)(r2 / Lx);
+        }
+        W[pl * Lx * Ly + (long long)y * Lx + x] = 0.0;
+    }
+}
+
+hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx, int Ly, hipStream_t s)
+{
+    if (nplanes <= 0) return hipSuccess;
+    if (Lx < 2 * nx || Ly < 2 * ny) return hipErrorInvalidValue;
+    const long long per = (long long)(Lx - 2 * nx + 1) * Ly + (long long)(Ly - 2 * ny + 1) * Lx;
+    const long long blocks = std::min<long long>((per * nplanes + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_gaps, dim3((unsigned)blocks), dim3(256), 0, s, W, nplanes, nx, ny, Lx, Ly);
+    return hipGetLastError();
+}
+
 // Zero n doubles with a kernel (used instead of a memset node on paths that a
 // caller may capture in a graph).
 __global__ __launch_bounds__(256) void k_zero64(double* __restrict__ p, long long n)
