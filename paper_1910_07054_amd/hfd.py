@@ -58,6 +58,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build the HIP library first "
                            "(python -m paper_1910_07054_amd.build)")
+    # torch first, so that the library binds to the HIP runtime torch has loaded
+    # (loading the library first can bring in a second runtime, and then the
+    # library's HIP calls fail on tensors torch allocated)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     i, d, p, ll = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
     sig = {
