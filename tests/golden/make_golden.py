@@ -10,6 +10,18 @@ FP64 field there, for the magnetization rounded to FP32 (the GPU input).
 Output: tests/golden/<name>_samples.npz with
   state [S], samples [S][3] (layer, iy, ix), h [S][3], hnorm_max (largest |h|_2
   over the sampled cells; the tests divide errors by it).
+
+    python tests/golden/make_golden.py C2full M0full
+
+writes tests/golden/<name>_full.npz: the whole FP64 brute-force field of
+state 0, [3][nz][ny][nx], stored rounded to FP32 (a relative change of at
+most 2^-24 per value, far below the 1e-5 tolerance it is compared at), and
+hnorm_max (largest |h|_2 over all cells, from the FP64 field).  M0 takes
+about ten minutes on 8 cores.
+
+    python tests/golden/make_golden.py C5grad
+
+writes the thickness gradients of all 16 C5 candidate stacks.
 """
 from __future__ import annotations
 
@@ -65,7 +77,20 @@ def make(name: str):
     print(f"wrote {out}", flush=True)
 
 
-def make_c5_grad(candidates=(0, 15)):
+def make_full(name: str):
+    """Every cell of state 0 by brute force (FP32-rounded m, as on the GPU)."""
+    wl = W.CONFIGS[name]()
+    m = wl.m[0].astype(np.float32).astype(np.float64)
+    t0 = time.time()
+    h = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], m)
+    print(f"{name}: full field in {time.time() - t0:.0f} s on {oracle.num_threads()} threads",
+          flush=True)
+    out = os.path.join(HERE, f"{name}_full.npz")
+    np.savez_compressed(out, h=h.astype(np.float32), hnorm_max=np.sqrt((h ** 2).sum(0)).max())
+    print(f"wrote {out}", flush=True)
+
+
+def make_c5_grad(candidates=tuple(range(16))):
     """Thickness gradient of L = mean over the free layer of h_z for the C5
     stacks (all ten thicknesses; gaps fixed), FP32-rounded m."""
     wl = W.c5()
@@ -90,5 +115,7 @@ if __name__ == "__main__":
     for n in names:
         if n == "C5grad":
             make_c5_grad()
+        elif n.endswith("full"):
+            make_full(n[:-4])
         else:
             make(n)

@@ -1,7 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark uses (whole batch in one call): sampled cells against stored oracle
-values (tests/golden, written by make_golden.py from the oracle only), and a
-property that holds at any size (uniform layers)."""
+benchmark uses (whole batch in one call): every cell of the 128x128x8 and
+256x256x8 stacks against the stored brute-force field, sampled cells of the
+others against stored oracle values (tests/golden, written by make_golden.py
+from the oracle only), and a property that holds at any size (uniform
+layers)."""
 import os
 
 import numpy as np
@@ -13,6 +15,9 @@ from paper_1910_07054_amd import workloads as W
 from hfd_testlib import plan_for
 
 pytestmark = pytest.mark.gpu
+# FP32 spectra, FP64 derivative tables and FP64 reductions: the gradient of
+# the mean free-layer h_z comes out within a few 1e-6 of the largest entry
+C5_GRAD_TOL = 2e-5
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -33,6 +38,21 @@ def _field_full(wl, flags):
     info = plan.info()
     plan.destroy()
     return h, info
+
+
+@pytest.mark.parametrize("name,split", [("C2", False), ("M0", False), ("M0", True)])
+def test_every_cell_matches_bruteforce(name, split):
+    """The whole field of state 0 against the oracle's direct sum over all
+    cell pairs (eq. of the discrete field, Sec. 3), error in the norm-wise
+    metric: max |h - h_ref| / max_cells |h_ref|_2."""
+    wl = W.CONFIGS[name]()
+    h, info = _field_full(wl, hfd.HFD_SPLIT_PASSES if split else hfd.HFD_FP32)
+    g = np.load(os.path.join(GOLD, f"{name}_full.npz"))
+    ref = g["h"].astype(np.float64)
+    got = h[0].double().cpu().numpy()
+    err = np.abs(got - ref).max() / float(g["hnorm_max"])
+    print(f"{name} split={split} fused={info.fused} every cell: max rel err {err:.2e}")
+    assert err < 1e-5
 
 
 @pytest.mark.parametrize("name,split", [("C2", False), ("M0", False), ("M0", True), ("C3", False),
@@ -84,9 +104,11 @@ def test_uniform_layers_equal_whole_layer_tensor(name):
     assert err < 1e-5, err
 
 
-def test_c5_thickness_gradient_matches_oracle():
-    """d(mean free-layer h_z)/d(thickness) for the C5 candidate stacks, all
-    candidates in one call; compared with stored oracle gradients."""
+@pytest.mark.parametrize("store", [False, True])
+def test_c5_thickness_gradient_matches_oracle(store):
+    """d(mean free-layer h_z)/d(thickness) for the 16 C5 candidate stacks, all
+    candidates in one call, derivative tables recomputed per call or stored;
+    compared with the stored oracle gradients of every candidate."""
     import torch
     path = os.path.join(GOLD, "C5_thickness_grad.npz")
     if not os.path.exists(path):
@@ -94,14 +116,17 @@ def test_c5_thickness_gradient_matches_oracle():
     g = np.load(path)
     wl = W.c5()
     free = wl.notes["free_layer"]
-    plan = plan_for(wl)
+    plan = plan_for(wl, flags=hfd.HFD_FP32 | (hfd.HFD_STORE_DTENSOR if store else 0))
     m = torch.from_numpy(wl.m.astype(np.float32)).cuda()
     gh = torch.zeros_like(m)
     gh[:, 2, free] = 1.0 / (wl.nx * wl.ny)
     _, gt = plan.vjp(m, gh, want_m=False, want_t=True)
     gt = gt.cpu().numpy()
     plan.destroy()
+    assert len(g["candidates"]) == wl.batch
+    errs = []
     for k, c in enumerate(g["candidates"]):
         ref = g["grad"][k]
-        err = np.abs(gt[c] - ref).max() / np.abs(ref).max()
-        assert err < 1e-4, (c, err, gt[c], ref)
+        errs.append(np.abs(gt[c] - ref).max() / np.abs(ref).max())
+    print(f"C5 thickness gradient (store={store}): max rel err over 16 candidates {max(errs):.2e}")
+    assert max(errs) < C5_GRAD_TOL, errs
