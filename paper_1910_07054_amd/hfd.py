@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "HFD_OK", -1: "HFD_EINVAL", -2: "HFD_ENOMEM", -3: "HFD_EHIP",
 EXPORTS = (
     "hfd_setup_tensor", "hfd_set_thickness", "hfd_demag_field", "hfd_demag_vjp", "hfd_time_stages",
     "hfd_autotune", "hfd_get_info", "hfd_export_fourier_tensor", "hfd_export_real_tensor",
-    "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error",
+    "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error", "hfd_set_path",
 )
 
 
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
         "hfd_demag_vjp": [p, p, p, p, p, i, p],
         "hfd_time_stages": [p, p, p, i, i, p, p, p, p, i],
         "hfd_autotune": [p, i, p, p, i],
+        "hfd_set_path": [p, i, i, i],
         "hfd_get_info": [p, ctypes.POINTER(Info)],
         "hfd_export_fourier_tensor": [p, i, p, ll],
         "hfd_export_real_tensor": [p, i, i, i, p, p],
@@ -108,6 +109,37 @@ def _dptr(t) -> int:
     return int(t.data_ptr())
 
 
+def check_field_tensor(t, name: str, nz: int, ny: int, nx: int, fp64: bool, batch_max: int,
+                       n_geom: int = 1, device=None, batch=None) -> int:
+    """Check a field-shaped tensor before its pointer goes to the library:
+    a torch tensor on the GPU (on ``device`` if given), float64 for FP64 plans
+    and float32 otherwise, contiguous, of shape [B, 3, nz, ny, nx] with
+    1 <= B <= batch_max and B a multiple of n_geom (and B == batch if given).
+    Returns B; raises ValueError (TypeError for a non-tensor)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU (got device {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the plan on {device}")
+    want = torch.float64 if fp64 else torch.float32
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want} for this plan (got {t.dtype})")
+    if t.dim() != 5 or tuple(t.shape[1:]) != (3, nz, ny, nx):
+        raise ValueError(f"{name} must have shape [B, 3, {nz}, {ny}, {nx}] (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    B = int(t.shape[0])
+    if B < 1 or B > batch_max:
+        raise ValueError(f"{name}: batch {B} outside [1, {batch_max}]")
+    if B % n_geom:
+        raise ValueError(f"{name}: batch {B} is not a multiple of n_geom = {n_geom}")
+    if batch is not None and B != batch:
+        raise ValueError(f"{name}: batch {B} differs from {batch}")
+    return B
+
+
 class Plan:
     """A geometry (nx, ny, dx, dy and one or more layer stacks) with its Fourier
     tensor on the GPU.  ``thickness`` and ``z_bottom`` are [nz] or [n_geom][nz]
@@ -127,6 +159,8 @@ class Plan:
         self.batch_max = int(batch_max)
         self.thickness = t.copy()
         self.z_bottom = None if z is None else z.copy()
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
         _check(lib.hfd_setup_tensor(ctypes.byref(h), self.nx, self.ny, self.dx, self.dy, self.nz,
                                     t.ctypes.data, None if z is None else z.ctypes.data,
@@ -159,13 +193,19 @@ class Plan:
         self.thickness = t.copy()
         self.z_bottom = None if z is None else z.copy()
 
+    def check(self, t, name: str, batch=None) -> int:
+        """Validate a [B, 3, nz, ny, nx] tensor for this plan (see check_field_tensor)."""
+        return check_field_tensor(t, name, self.nz, self.ny, self.nx, self.fp64, self.batch_max,
+                                  self.n_geom, self.device, batch)
+
     # -- field ---------------------------------------------------------------
     def field(self, m, out=None, stream=None):
         """h = -N * m for m of shape [B, 3, nz, ny, nx] (torch, on the GPU)."""
         import torch
+        B = self.check(m, "m")
         if out is None:
-            out = torch.empty_like(m)
-        B = m.shape[0]
+            out = torch.empty_like(m, memory_format=torch.contiguous_format)
+        self.check(out, "out", B)
         _check(load().hfd_demag_field(self.handle, _dptr(m), _dptr(out), int(B),
                                       _stream_handle(stream)))
         return out
@@ -173,8 +213,12 @@ class Plan:
     def vjp(self, m, grad_h, want_m: bool = True, want_t: bool = True, stream=None):
         """(grad_m, grad_thickness[B, nz] float64) of <grad_h, h(m, t)>."""
         import torch
-        B = grad_h.shape[0]
-        gm = torch.empty_like(grad_h) if want_m else None
+        B = self.check(grad_h, "grad_h")
+        if want_t:
+            if m is None:
+                raise ValueError("m is needed for the thickness gradient")
+            self.check(m, "m", B)
+        gm = torch.empty_like(grad_h, memory_format=torch.contiguous_format) if want_m else None
         gt = torch.empty((B, self.nz), dtype=torch.float64, device=grad_h.device) if want_t else None
         _check(load().hfd_demag_vjp(self.handle, _dptr(m) if m is not None else None, _dptr(grad_h),
                                     _dptr(gm) if gm is not None else None,
@@ -185,7 +229,7 @@ class Plan:
     def forward_spectrum(self, m, stream=None):
         import torch
         inf = self.info()
-        B = m.shape[0]
+        B = self.check(m, "m")
         dt = torch.complex128 if self.fp64 else torch.complex64
         out = torch.empty((B, 3, self.nz, inf.Lx // 2, inf.Ly), dtype=dt, device=m.device)
         _check(load().hfd_forward_spectrum(self.handle, _dptr(m), _dptr(out),
@@ -194,6 +238,8 @@ class Plan:
         return out
 
     def time_stages(self, m, h, reps: int = 20, stream=None):
+        B = self.check(m, "m")
+        self.check(h, "h", B)
         ms = (ctypes.c_double * 8)()
         n = ctypes.c_int()
         names = ctypes.create_string_buffer(256)
@@ -206,6 +252,10 @@ class Plan:
         rep = ctypes.create_string_buffer(1024)
         _check(load().hfd_autotune(self.handle, int(batch), _stream_handle(stream), rep, 1024))
         return rep.value.decode()
+
+    def set_path(self, batch: int, path: int, x_tile: int = 0):
+        """Pin the field path and x-pass tile for `batch` states (path < 0: unpin)."""
+        _check(load().hfd_set_path(self.handle, int(batch), int(path), int(x_tile)))
 
     # -- inspection ----------------------------------------------------------
     def export_fourier_tensor(self, geom: int = 0) -> np.ndarray:
@@ -253,7 +303,9 @@ def _autograd():
             tt = thickness.detach().cpu().numpy().reshape(plan.n_geom, plan.nz)
             if not np.array_equal(tt, plan.thickness):
                 raise ValueError("thickness differs from the plan geometry; call plan.set_thickness")
+            m = m.contiguous()
             ctx.plan = plan
+            ctx.t_device, ctx.t_dtype, ctx.t_shape = thickness.device, thickness.dtype, thickness.shape
             ctx.save_for_backward(m)
             return plan.field(m)
 
@@ -265,8 +317,10 @@ def _autograd():
             gm, gt = plan.vjp(m, grad_h.contiguous(), want_m=need_m, want_t=need_t)
             gthick = None
             if need_t:
+                # states b * bpg .. (b + 1) * bpg - 1 use stack b: their gradients add up
                 B = gt.shape[0]
                 gthick = gt.reshape(plan.n_geom, B // plan.n_geom, plan.nz).sum(1)
+                gthick = gthick.to(device=ctx.t_device, dtype=ctx.t_dtype).reshape(ctx.t_shape)
             return gm, gthick, None
 
     return DemagField
