@@ -113,9 +113,27 @@ hfd_status hfd_setup_tensor(hfd_plan *out, int nx, int ny, double dx, double dy,
                             const double *thickness, const double *z_bottom, int n_geom,
                             int batch_max, unsigned flags, void *stream);
 
-/* Rebuild the tensor of an existing plan for new thicknesses / bottoms (same
- * nx, ny, dx, dy, nz, n_geom; same conventions as hfd_setup_tensor).  Blocks
- * until the new tensor is ready on `stream`. */
+/*
+ * Rebuild the tensor of an existing plan for new thicknesses / bottoms (same
+ * nx, ny, dx, dy, nz, n_geom; same conventions as hfd_setup_tensor).  This is
+ * the step of the layer-thickness optimisation of Sec. 4 (Newton iteration on
+ * one layer thickness until the mean field in the free layer vanishes): the
+ * geometry changes, the lateral grid stays.  Blocks until the new tensor is
+ * ready on `stream`; allocates nothing (the setup scratch belongs to the
+ * plan) except that the thickness-derivative tables grow when the new
+ * geometry has more distinct interface offsets than any earlier one.
+ *
+ * The stored Fourier tensor is rewritten in place, so a HIP graph that
+ * captured hfd_demag_field (or hfd_demag_vjp without grad_thickness) stays
+ * valid and computes the new geometry on its next replay.  A graph that
+ * captured hfd_demag_vjp with grad_thickness must be captured again: its
+ * kernels are sized by the per-geometry offset counts.
+ *
+ * Invalid arguments return HFD_EINVAL with the plan unchanged.  A failure
+ * after validation (device allocation or kernel error) leaves the plan
+ * unusable: field and vjp calls return HFD_EINVAL until a later
+ * hfd_set_thickness succeeds.
+ */
 hfd_status hfd_set_thickness(hfd_plan plan, const double *thickness, const double *z_bottom,
                              void *stream);
 
@@ -127,7 +145,10 @@ hfd_status hfd_set_thickness(hfd_plan plan, const double *thickness, const doubl
 hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, void *stream);
 
 /*
- * Vector-Jacobian product of h = h(m, t) for an upstream gradient grad_h:
+ * Vector-Jacobian product of h = h(m, t) for an upstream gradient grad_h.
+ * The paper optimises a layer thickness by Newton's method on the mean field
+ * in the free layer (Sec. 4) without saying how the derivative is formed;
+ * this call supplies it analytically, together with the gradient in m:
  *   grad_m = (dh/dm)^T grad_h           (device [batch][3][nz][ny][nx]), and
  *   grad_thickness[b][k] = d <grad_h_b, h_b> / d t_k   (device FP64
  *                                       [batch][nz]) for a stack whose gaps stay
@@ -138,6 +159,8 @@ hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, voi
  * evaluated in FP64 and transformed like the tensor.  grad_thickness returns
  * HFD_ENOTSUP on equidistant plans and when one kx row of the derivative
  * table (distinct interface offsets x 6 x (Ly/2+1) values) exceeds 2 GiB.
+ * m may be NULL when grad_thickness is NULL.  Allocates nothing; the derivative
+ * tables are rebuilt inside the call unless the plan has HFD_STORE_DTENSOR.
  */
 hfd_status hfd_demag_vjp(hfd_plan plan, const void *m, const void *grad_h, void *grad_m,
                          double *grad_thickness, int batch, void *stream);
@@ -162,6 +185,15 @@ hfd_status hfd_time_stages(hfd_plan plan, const void *m, void *h, int batch, int
  * so it must not be captured in a graph.  `report` (host buffer) receives the
  * timings and the choice as text, e.g. "batch=1 fused=0.047ms ... -> fused". */
 hfd_status hfd_autotune(hfd_plan plan, int batch, void *stream, char *report, int report_len);
+
+/* Pin the field configuration used for `batch` states instead of timing it
+ * (hfd_autotune): path 0 fused y-pass, 1 five-pass with per-frequency mixing,
+ * 2 five-pass with batched FP32 mixing, 3 five-pass with split-BF16 MFMA
+ * mixing (plans created with HFD_MIX_SPLIT_BF16), 4 equidistant plans; x_tile
+ * = rows per block of the x passes (0 = default tile, or 4, 8, 16, 24, 32
+ * where the block fits).  path < 0 drops the pinned choice.  Host only;
+ * HFD_EINVAL for a configuration the plan cannot run. */
+hfd_status hfd_set_path(hfd_plan plan, int batch, int path, int x_tile);
 
 /* Plan description (host). */
 typedef struct {

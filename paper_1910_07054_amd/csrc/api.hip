@@ -20,6 +20,26 @@
 
 using namespace hfd;
 
+namespace hfd {
+hipError_t ensure_lds_limit(const void* kernel, int bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> done;  // (kernel, device) -> limit set
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(kernel, dev);
+    const auto it = done.find(key);
+    if (it != done.end() && it->second >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    done[key] = bytes;
+    return hipSuccess;
+}
+}  // namespace hfd
+
 namespace {
 
 thread_local std::string g_err;
@@ -132,7 +152,20 @@ struct hfd_plan_s {
     // FP32 mixing, 3 five-pass split-BF16 MFMA mixing, 4 equidistant (z FFT);
     // default from the flags, per-batch choice from hfd_autotune
     int path = 0;
-    std::map<int, int> tuned;
+    struct Tune {
+        int path, xty;
+    };
+    std::map<int, Tune> tuned;
+    // false while hfd_set_thickness rebuilds the plan and after it failed:
+    // field and vjp calls are refused until a later set succeeds
+    bool ready = true;
+    // tensor-setup scratch, allocated once with the plan (set_thickness reuses it)
+    double* sW = nullptr;       // real-space FP64 tables [chunk][6][Ly][Lx]
+    void* sF = nullptr;         // their spectra
+    void* spg = nullptr;        // pair geometries
+    double* sscale = nullptr;   // per pair scale
+    double* sQ2 = nullptr;      // equidistant plans: per-offset spectra
+    int schunk = 0, spg_cap = 0;
 };
 
 namespace {
@@ -149,6 +182,15 @@ hfd_status check_plan(hfd_plan p)
         if (!g_plans.count(p)) return fail(HFD_EHANDLE, "plan handle was destroyed or never created");
     }
     if (p->magic != kMagic) return fail(HFD_EHANDLE, "plan handle is corrupted");
+    return HFD_OK;
+}
+
+hfd_status check_ready(hfd_plan p)
+{
+    HFD_TRY(check_plan(p));
+    if (!p->ready)
+        return fail(HFD_EINVAL, "the plan's tensor is not valid (the last hfd_set_thickness failed): "
+                                "call hfd_set_thickness again or destroy the plan");
     return HFD_OK;
 }
 
@@ -214,7 +256,8 @@ void free_plan_memory(hfd_plan p)
     if (p->twx == p->twx64) p->twx = nullptr;  // FP64 plans share the FP64 tables
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
-                    p->D, p->itab, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz};
+                    p->D, p->itab, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz,
+                    p->sW, p->sF, p->spg, p->sscale, p->sQ2};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
@@ -227,6 +270,11 @@ void free_plan_memory(hfd_plan p)
     p->zeta_dev = nullptr;
     p->partial = nullptr;
     p->Bc = p->twz = nullptr;
+    p->sW = nullptr;
+    p->sF = nullptr;
+    p->spg = nullptr;
+    p->sscale = nullptr;
+    p->sQ2 = nullptr;
 }
 
 // twiddle table exp(-2 pi i m / L), m in [0, L), in FP64 (exact octant reduction)
@@ -276,49 +324,57 @@ hfd_status upload_twiddles(hfd_plan p, hipStream_t s)
     return HFD_OK;
 }
 
+// Tensor-setup scratch, allocated once per plan: real-space tables and their
+// spectra for a chunk of pair geometries (256 MB each at most), the pair list
+// and scales, and for equidistant plans the per-offset spectra.
+hfd_status alloc_setup_scratch(hfd_plan p)
+{
+    const long long per_pair = 6LL * p->Lx * p->Ly * 8;  // FP64 real arrays per pair
+    const int ngeo = std::max(p->P, 2 * p->nz - 1);         // distinct geometries per stack, at most
+    const long long budget = 256LL << 20;
+    p->schunk = (int)std::max(1LL, std::min<long long>(ngeo, budget / per_pair));
+    p->spg_cap = ngeo;
+    HFD_TRY(dev_alloc(&p->sW, (size_t)p->schunk * per_pair, "tensor setup (real space)"));
+    HFD_TRY(dev_alloc(&p->sF, (size_t)p->schunk * per_pair, "tensor setup (spectra)"));
+    HFD_TRY(dev_alloc(&p->spg, sizeof(PairGeoH) * (size_t)ngeo, "pair table"));
+    HFD_TRY(dev_alloc(&p->sscale, sizeof(double) * (size_t)ngeo, "pair scales"));
+    if (p->eq3d)
+        HFD_TRY(dev_alloc(&p->sQ2, sizeof(double) * 6 * (size_t)p->QX * p->QY * (2 * p->nz - 1),
+                          "per-offset spectra"));
+    return HFD_OK;
+}
+
 // FP64 2D spectra (x and y transforms of the zero-padded real-space tensor,
-// 6 components each) of the cuboid-pair geometries `geos`, in chunks that fit
-// a 512 MB scratch budget; after each chunk pack(first, count, F) enqueues the
+// 6 components each) of the cuboid-pair geometries `geos`, in chunks of the
+// plan's setup scratch; after each chunk pack(first, count, F) enqueues the
 // packing of spectra F[count][6][M][Ly] (complex, interleaved re/im doubles).
 // Synchronizes the stream at the end.
 template <class Pack>
 hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
 {
     const int n = (int)geos.size();
+    if (n > p->spg_cap) return fail(HFD_EINVAL, "internal: more pair geometries than the setup scratch holds");
     const long long plane = (long long)p->Lx * p->Ly;
-    const long long per_pair = 6 * plane * 8;  // FP64 real arrays per pair (same for the spectra)
-    const long long budget = 512LL << 20;
-    const int CP = (int)std::max(1LL, std::min<long long>(n, budget / per_pair));
-    double* W = nullptr;
-    void* F = nullptr;
-    PairGeoH* pg = nullptr;
-    hfd_status st = HFD_OK;
-    do {
-        st = dev_alloc(&W, (size_t)CP * per_pair, "tensor setup (real space)");
-        if (st) break;
-        st = dev_alloc(&F, (size_t)CP * per_pair, "tensor setup (spectra)");
-        if (st) break;
-        st = dev_alloc(&pg, sizeof(PairGeoH) * (size_t)n, "pair table");
-        if (st) break;
-        hipError_t e = hipMemcpyAsync(pg, geos.data(), sizeof(PairGeoH) * n, hipMemcpyHostToDevice, s);
-        for (int u0 = 0; u0 < n && e == hipSuccess; u0 += CP) {
-            const int np = std::min(CP, n - u0);
-            e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
-            if (e == hipSuccess)
-                e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
-            if (e == hipSuccess)
-                e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
-            if (e == hipSuccess)
-                e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
-            if (e == hipSuccess) e = pack(u0, np, (const double*)F);
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
-    } while (0);
-    if (W) (void)hipFree(W);
-    if (F) (void)hipFree(F);
-    if (pg) (void)hipFree(pg);
-    return st;
+    const long long per_pair = 6 * plane * 8;
+    const int CP = p->schunk;
+    double* W = p->sW;
+    void* F = p->sF;
+    PairGeoH* pg = (PairGeoH*)p->spg;
+    hipError_t e = hipMemcpyAsync(pg, geos.data(), sizeof(PairGeoH) * n, hipMemcpyHostToDevice, s);
+    for (int u0 = 0; u0 < n && e == hipSuccess; u0 += CP) {
+        const int np = std::min(CP, n - u0);
+        e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
+        if (e == hipSuccess)
+            e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
+        if (e == hipSuccess)
+            e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
+        if (e == hipSuccess)
+            e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
+        if (e == hipSuccess) e = pack(u0, np, (const double*)F);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
+    return HFD_OK;
 }
 
 // Build the Fourier tensor of every stack (FP64 setup, stored in plan precision).
@@ -327,9 +383,8 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
 hfd_status build_tensor(hfd_plan p, hipStream_t s)
 {
     const long long plane = (long long)p->Lx * p->Ly;
-    double* scale = nullptr;
-    hfd_status st = dev_alloc(&scale, sizeof(double) * (size_t)p->P, "pair scales");
-    if (st) return st;
+    double* scale = p->sscale;
+    hfd_status st = HFD_OK;
     std::vector<PairGeoH> ug;
     std::vector<int> uid((size_t)p->P);
     std::vector<double> hs((size_t)p->P);
@@ -368,7 +423,6 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
         });
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(scale);
     if (st) return st;
     // layer parameters: 1/t and the self-pair trace -t/(Lx Ly)
     std::vector<double> lp((size_t)p->G * 2 * p->nz);
@@ -404,13 +458,11 @@ hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
     std::vector<PairGeoH> geos((size_t)nd);
     for (int k = 0; k < nd; ++k) geos[k] = {t, t, (double)(k - (p->nz - 1)) * pitch, 0.0};
     std::vector<double> hs((size_t)nd, -1.0 / (double)plane);
-    double* scale = nullptr;
-    double* Q2 = nullptr;
+    double* scale = p->sscale;
+    double* Q2 = p->sQ2;
     const size_t per = (size_t)6 * p->QX * p->QY;
-    hfd_status st = dev_alloc(&scale, sizeof(double) * nd, "offset scales");
-    if (st == HFD_OK) st = dev_alloc(&Q2, sizeof(double) * per * nd, "per-offset spectra");
-    if (st == HFD_OK &&
-        hipMemcpyAsync(scale, hs.data(), sizeof(double) * nd, hipMemcpyHostToDevice, s) != hipSuccess)
+    hfd_status st = HFD_OK;
+    if (hipMemcpyAsync(scale, hs.data(), sizeof(double) * nd, hipMemcpyHostToDevice, s) != hipSuccess)
         st = fail(HFD_EHIP, "tensor setup: scale upload failed");
     if (st == HFD_OK)
         st = tensor_spectra(p, geos, s, [&](int u0, int np, const double* F) -> hipError_t {
@@ -423,8 +475,6 @@ hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
         if (e != hipSuccess) st = fail(HFD_EHIP, std::string("tensor setup: ") + hipGetErrorString(e));
     }
     (void)hipStreamSynchronize(s);
-    if (scale) (void)hipFree(scale);
-    if (Q2) (void)hipFree(Q2);
     return st;
 }
 
@@ -554,7 +604,11 @@ void derivative_offsets(hfd_plan p, bool shared, std::vector<double>& zeta, std:
         for (int i = 0; i < count[k]; ++i) zeta[(size_t)k * nmax + i] = tables[k][i];
 }
 
-// Allocate (or re-allocate) the derivative buffers and upload the offsets.
+// Allocate (or grow) the derivative buffers and upload the offsets.  New
+// buffers are allocated before the old ones are released, so a failure leaves
+// the previous buffers in place (the plan is then marked not ready by the
+// caller).  Buffers only grow: a geometry with fewer distinct offsets keeps
+// the allocated stride nzeta_max.
 hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
 {
     std::vector<double> zeta;
@@ -563,14 +617,20 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     // stored: one table shared by all stacks; recomputed: one table per stack,
     // built into the same buffer before that stack's reduction
     derivative_offsets(p, (p->flags & HFD_STORE_DTENSOR) != 0, zeta, itab, count, nmax);
-    const long long per_table = (long long)nmax * 6 * p->QX * p->QY;
+    auto swap_in = [](auto*& slot, auto* fresh) {
+        if (slot) (void)hipFree(slot);
+        slot = fresh;
+    };
     if (nmax > p->nzeta_max || !p->D) {
-        if (p->D) (void)hipFree(p->D);
-        if (p->zeta_dev) (void)hipFree(p->zeta_dev);
-        p->D = nullptr;
-        p->zeta_dev = nullptr;
-        HFD_TRY(dev_alloc(&p->D, (size_t)per_table * p->rsz, "derivative tensor"));
-        HFD_TRY(dev_alloc(&p->zeta_dev, sizeof(double) * zeta.size(), "derivative offsets"));
+        const long long per_table = (long long)nmax * 6 * p->QX * p->QY;
+        void* nD = nullptr;
+        double* nz_dev = nullptr;
+        HFD_TRY(dev_alloc(&nD, (size_t)per_table * p->rsz, "derivative tensor"));
+        hfd_status st = dev_alloc(&nz_dev, sizeof(double) * count.size() * (size_t)nmax,
+                                  "derivative offsets");
+        if (st) { (void)hipFree(nD); return st; }
+        swap_in(p->D, nD);
+        swap_in(p->zeta_dev, nz_dev);
         p->nzeta_max = nmax;
     }
     if (!p->itab) HFD_TRY(dev_alloc(&p->itab, sizeof(int) * itab.size(), "interface table"));
@@ -579,15 +639,19 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     const long long per_z = 6 * plane * 8;
     const int chunk = (int)std::max(1LL, std::min<long long>(nmax, (256LL << 20) / per_z));
     if (chunk > p->dchunk) {
-        if (p->dW) (void)hipFree(p->dW);
-        if (p->dF) (void)hipFree(p->dF);
-        if (p->dscale) (void)hipFree(p->dscale);
-        p->dW = nullptr;
-        p->dF = nullptr;
-        p->dscale = nullptr;
-        HFD_TRY(dev_alloc(&p->dW, (size_t)chunk * per_z, "derivative scratch"));
-        HFD_TRY(dev_alloc(&p->dF, (size_t)chunk * per_z, "derivative scratch"));
-        HFD_TRY(dev_alloc(&p->dscale, sizeof(double) * chunk, "derivative scale"));
+        double *nW = nullptr, *nsc = nullptr;
+        void* nF = nullptr;
+        hfd_status st = dev_alloc(&nW, (size_t)chunk * per_z, "derivative scratch");
+        if (st == HFD_OK) st = dev_alloc(&nF, (size_t)chunk * per_z, "derivative scratch");
+        if (st == HFD_OK) st = dev_alloc(&nsc, sizeof(double) * chunk, "derivative scale");
+        if (st) {
+            if (nW) (void)hipFree(nW);
+            if (nF) (void)hipFree(nF);
+            return st;
+        }
+        swap_in(p->dW, nW);
+        swap_in(p->dF, nF);
+        swap_in(p->dscale, nsc);
         std::vector<double> sc((size_t)chunk, -1.0 / (double)plane);
         HFD_HIP(hipMemcpyAsync(p->dscale, sc.data(), sizeof(double) * chunk, hipMemcpyHostToDevice, s));
         p->dchunk = chunk;
@@ -606,10 +670,10 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     // partial sums of the reduction
     const int ntiles = tgrad_tiles(p->M, p->Ly);
     if (ntiles != p->ntiles || !p->partial) {
-        if (p->partial) (void)hipFree(p->partial);
-        p->partial = nullptr;
-        HFD_TRY(dev_alloc(&p->partial, sizeof(double) * (size_t)p->batch_max * ntiles * 2 * p->nz,
+        double* np_ = nullptr;
+        HFD_TRY(dev_alloc(&np_, sizeof(double) * (size_t)p->batch_max * ntiles * 2 * p->nz,
                           "reduction partials"));
+        swap_in(p->partial, np_);
         p->ntiles = ntiles;
     }
     HFD_HIP(hipStreamSynchronize(s));
@@ -661,7 +725,20 @@ hfd_status check_field_args(hfd_plan p, const void* a, const void* b, int batch,
 int path_for(hfd_plan p, int batch)
 {
     auto it = p->tuned.find(batch);
-    return it != p->tuned.end() ? it->second : p->path;
+    return it != p->tuned.end() ? it->second.path : p->path;
+}
+
+// rows per block of the x passes: the tuned choice, else the largest compiled
+// tile that still gives every CU at least one block
+int xty_for(hfd_plan p, int batch)
+{
+    auto it = p->tuned.find(batch);
+    if (it != p->tuned.end()) return it->second.xty;
+    const long long rows = (long long)batch * 3 * p->nz * p->ny;
+    int best = 0;
+    for (int ty : {8, 16, 24, 32})
+        if (x_tile_supported(p->fp64, p->Lx, ty) && (rows + ty - 1) / ty >= 256) best = ty;
+    return best;
 }
 
 const char* path_name(int path)
@@ -679,12 +756,13 @@ const char* path_name(int path)
 // `only` >= 0 launches the kernels of that stage alone (stage timing).
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
                      hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1,
-                     int only = -1)
+                     int only = -1, int xty = -1)
 {
     const int S = 3 * p->nz;
     const int nsig = batch * S;
     const int bpg = batch / p->G;
     if (path < 0) path = path_for(p, batch);
+    if (xty < 0) xty = xty_for(p, batch);
     if ((path == 2 || path == 3) && !mix_batched_supported(p->nz, batch, p->G)) path = 1;
     int k = 0;
     auto mark = [&]() {
@@ -694,7 +772,7 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     auto on = [&]() { return only < 0 || only == k; };
     if (on())
         HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
-                            nsig, p->twx, s));
+                            nsig, p->twx, s, xty));
     mark();
     if (path == 0) {
         if (on())
@@ -731,7 +809,7 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     }
     if (on())
         HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
-                            nsig, p->twx, s));
+                            nsig, p->twx, s, xty));
     mark();
     if (nstage) *nstage = k;
     return HFD_OK;
@@ -844,6 +922,8 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         }
         st = upload_twiddles(p, s);
         if (st) break;
+        st = alloc_setup_scratch(p);
+        if (st) break;
         if (p->eq3d) {
             st = build_tensor3d(p, s);
             break;
@@ -879,10 +959,17 @@ hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* 
     if (p->eq3d) HFD_TRY(check_equidistant(p->nz, p->G, t, z));
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
+    // from here on the stored tensor is being replaced: the plan is unusable
+    // until the rebuild has completed
+    p->ready = false;
     p->thick = t;
     p->zbot = z;
     hipStream_t s = (hipStream_t)stream;
-    if (p->eq3d) return build_tensor3d(p, s);
+    if (p->eq3d) {
+        HFD_TRY(build_tensor3d(p, s));
+        p->ready = true;
+        return HFD_OK;
+    }
     HFD_TRY(build_tensor(p, s));
     HFD_TRY(setup_derivatives(p, s));
     if (p->flags & HFD_STORE_DTENSOR) {
@@ -890,12 +977,13 @@ hfd_status hfd_set_thickness(hfd_plan p, const double* thickness, const double* 
         HFD_HIP(hipStreamSynchronize(s));
         p->d_valid = true;
     }
+    p->ready = true;
     return HFD_OK;
 }
 
 hfd_status hfd_demag_field(hfd_plan p, const void* m, void* h, int batch, void* stream)
 {
-    HFD_TRY(check_plan(p));
+    HFD_TRY(check_ready(p));
     HFD_TRY(check_field_args(p, m, h, batch, "m", "h"));
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
@@ -905,7 +993,7 @@ hfd_status hfd_demag_field(hfd_plan p, const void* m, void* h, int batch, void* 
 hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* grad_m,
                          double* grad_thickness, int batch, void* stream)
 {
-    HFD_TRY(check_plan(p));
+    HFD_TRY(check_ready(p));
     if (!grad_m && !grad_thickness) return fail(HFD_EINVAL, "grad_m and grad_thickness are both NULL");
     if (p->eq3d && grad_thickness)
         return fail(HFD_ENOTSUP, "thickness gradients need the non-equidistant plan (no HFD_EQUIDISTANT)");
@@ -932,7 +1020,13 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     HFD_HIP(launch_xfwd(p->fp64, p->Lx, grad_h, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
     HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Hh, p->ny, ncols, p->twy, s));
     const int bpg = batch / p->G;
-    if (p->d_valid) {
+    const bool stored = (p->flags & HFD_STORE_DTENSOR) != 0;
+    if (stored && !p->d_valid) {
+        // stored mode whose table is not built yet: build the shared table once
+        HFD_TRY(compute_derivatives(p, 0, s));
+        p->d_valid = true;
+    }
+    if (stored) {
         HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
                              p->D, p->nzeta_max, p->itab, p->itab_stride, p->lp, bpg, p->QX, p->QY,
                              p->partial, s));
@@ -953,7 +1047,7 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
 hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int reps, void* stream,
                            double* ms_per_stage, int* n_stages, char* names, int name_len)
 {
-    HFD_TRY(check_plan(p));
+    HFD_TRY(check_ready(p));
     HFD_TRY(check_field_args(p, m, h, batch, "m", "h"));
     if (reps < 1 || !ms_per_stage || !n_stages) return fail(HFD_EINVAL, "bad timing arguments");
     DeviceGuard dg;
@@ -996,7 +1090,7 @@ hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int re
 
 hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int report_len)
 {
-    HFD_TRY(check_plan(p));
+    HFD_TRY(check_ready(p));
     if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
     if (batch % p->G) return fail(HFD_EINVAL, "batch must be a multiple of n_geom");
     DeviceGuard dg;
@@ -1025,6 +1119,7 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     hipEvent_t e0, e1;
     std::string rep = "batch=" + std::to_string(batch);
     int best = p->path;
+    int best_ty = xty_for(p, batch);
     double best_ms = 1e30;
     do {
         if (hipMemsetAsync(m, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
@@ -1032,21 +1127,47 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
             st = fail(HFD_EHIP, "autotune setup failed");
             break;
         }
-        for (int path : cand) {
-            for (int w = 0; w < 2 && st == HFD_OK; ++w) st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path);
+        // time one configuration: two warm-up evaluations, then 10 back to back
+        auto time_cfg = [&](int path, int xty, double& per) -> hfd_status {
+            hfd_status t = HFD_OK;
+            for (int w = 0; w < 2 && t == HFD_OK; ++w)
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty);
             const int reps = 10;
             (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps && st == HFD_OK; ++r) st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path);
+            for (int r = 0; r < reps && t == HFD_OK; ++r)
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty);
             (void)hipEventRecord(e1, s);
-            if (st) break;
-            if (hipEventSynchronize(e1) != hipSuccess) { st = fail(HFD_EHIP, "autotune sync failed"); break; }
+            if (t) return t;
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(HFD_EHIP, "autotune sync failed");
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            const double per = ms / reps;
+            per = ms / reps;
+            return HFD_OK;
+        };
+        // stage 1: the field path, x passes with their default tile
+        const int xdef = xty_for(p, batch);
+        for (int path : cand) {
+            double per = 0;
+            st = time_cfg(path, xdef, per);
+            if (st) break;
             char buf[96];
             std::snprintf(buf, sizeof buf, " %s=%.4fms", path_name(path), per);
             rep += buf;
             if (per < best_ms) { best_ms = per; best = path; }
+        }
+        // stage 2: rows per block of the x passes for the chosen path
+        if (st == HFD_OK) {
+            rep += " | x tile:";
+            for (int ty : {0, 4, 8, 16, 24, 32}) {
+                if (!x_tile_supported(p->fp64, p->Lx, ty) || ty == xdef) continue;
+                double per = 0;
+                st = time_cfg(best, ty, per);
+                if (st) break;
+                char buf[64];
+                std::snprintf(buf, sizeof buf, " %d=%.4fms", ty, per);
+                rep += buf;
+                if (per < best_ms) { best_ms = per; best_ty = ty; }
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1055,9 +1176,32 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     (void)hipFree(m);
     (void)hipFree(h);
     if (st) return st;
-    p->tuned[batch] = best;
-    rep += std::string(" -> ") + path_name(best);
+    p->tuned[batch] = {best, best_ty};
+    rep += std::string(" -> ") + path_name(best) + " x" + std::to_string(best_ty);
     if (report && report_len > 0) std::snprintf(report, (size_t)report_len, "%s", rep.c_str());
+    return HFD_OK;
+}
+
+hfd_status hfd_set_path(hfd_plan p, int batch, int path, int x_tile)
+{
+    HFD_TRY(check_plan(p));
+    if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
+    if (batch % p->G) return fail(HFD_EINVAL, "batch must be a multiple of n_geom");
+    if (path < 0) {
+        p->tuned.erase(batch);
+        return HFD_OK;
+    }
+    bool ok = false;
+    if (p->eq3d) ok = path == 4;
+    else if (path == 0) ok = !(p->flags & HFD_SPLIT_PASSES) && fused_supported(p->fp64, p->Ly, p->nz, nullptr);
+    else if (path == 1) ok = true;
+    else if (path == 2) ok = !p->fp64;
+    else if (path == 3) ok = p->bf16;
+    if (!ok) return fail(HFD_EINVAL, "path " + std::to_string(path) + " is not available for this plan");
+    if (!x_tile_supported(p->fp64, p->Lx, x_tile))
+        return fail(HFD_EINVAL, "x tile " + std::to_string(x_tile) + " is not compiled for Lx = " +
+                                    std::to_string(p->Lx));
+    p->tuned[batch] = {path, x_tile};
     return HFD_OK;
 }
 
@@ -1078,7 +1222,7 @@ hfd_status hfd_get_info(hfd_plan p, hfd_info* info)
 
 hfd_status hfd_export_fourier_tensor(hfd_plan p, int geom, void* dst, long long dst_bytes)
 {
-    HFD_TRY(check_plan(p));
+    HFD_TRY(check_ready(p));
     if (geom < 0 || geom >= p->G) return fail(HFD_EINVAL, "geom out of range");
     const long long bytes = p->q_geom_stride * (long long)p->rsz;
     if (!dst || dst_bytes < bytes) return fail(HFD_EINVAL, "dst too small (need " + std::to_string(bytes) + " bytes)");

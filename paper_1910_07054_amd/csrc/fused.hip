@@ -21,12 +21,9 @@ hipError_t fused_a(int nz, void* X, int ny, int M, int B, const void* Q, long lo
                    int QY, const void* lp, int bpg, const void* tw, hipStream_t s)
 {
     const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
-    static bool attr_done = false;  // the attribute is set once to the largest possible size
-    if (lds > 65536 && !attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    if (lds > 65536) {  // the limit is raised once to the largest possible size
+        hipError_t e = ensure_lds_limit((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>, 163840);
         if (e != hipSuccess) return e;
-        attr_done = true;
     }
     hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, B), dim3(FusedShape<LY>::NT), lds,
                        s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QX, QY, (const R*)lp, bpg,

@@ -9,13 +9,21 @@ namespace hfd {
 constexpr int kMinL = 8;
 constexpr int kMaxL = 4096;
 
-// x pass, forward / inverse (R = float if !fp64 else double)
+// Raise the dynamic-LDS limit of `kernel` on the current device to `bytes`
+// (no-op up to 64 KB).  Remembered per (kernel, device) once the runtime has
+// accepted it; thread safe.
+hipError_t ensure_lds_limit(const void* kernel, int bytes);
+
+// x pass, forward / inverse (R = float if !fp64 else double) over nsig * ny
+// rows; ty = rows per block (0: the default tile; else one of 4, 8, 16, 24,
+// 32 where x_tile_supported)
+bool x_tile_supported(bool fp64, int LX, int ty);
 hipError_t launch_xfwd(bool fp64, int LX, const void* in, void* out, int nx, int ny,
                        long long in_sig_stride, int in_row_stride, int nsig, const void* twx,
-                       hipStream_t s);
+                       hipStream_t s, int ty = 0);
 hipError_t launch_xinv(bool fp64, int LX, const void* in, void* out, int nx, int ny,
                        long long out_sig_stride, int out_row_stride, int nsig, const void* twx,
-                       hipStream_t s);
+                       hipStream_t s, int ty = 0);
 
 // y pass on columns: forward (n_in values padded to LY) / inverse (first n_out kept)
 hipError_t launch_yfwd(bool fp64, int LY, const void* in, void* out, int n_in, long long ncols,

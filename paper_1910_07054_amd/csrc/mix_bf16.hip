@@ -281,13 +281,8 @@ hipError_t launch_batched_nz(const void* Mh, void* Hh, int M, int LY, int G, con
 {
     using SH = BatchedShape<NZ>;
     const size_t lds = SH::lds(MFMA);
-    static bool attr_done = false;
-    if (!attr_done && lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_mix_batched<MFMA, NZ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
+    hipError_t e = ensure_lds_limit((const void*)k_mix_batched<MFMA, NZ>, (int)lds);
+    if (e != hipSuccess) return e;
     dim3 grid((LY + SH::TK - 1) / SH::TK, M - 1, G);
     hipLaunchKernelGGL((k_mix_batched<MFMA, NZ>), grid, dim3(256), lds, s, (const cpx<float>*)Mh,
                        (cpx<float>*)Hh, M, LY, (const float*)Q, qgs, QY, (const float*)lp, bpg,

@@ -74,3 +74,54 @@ def test_vjp_graph_replays_match_eager(store):
 
     _replay_check(plan, run, make)
     plan.destroy()
+
+
+@pytest.mark.parametrize("flags", [hfd.HFD_FP32, hfd.HFD_SPLIT_PASSES], ids=["fused", "five_pass"])
+def test_field_graph_follows_set_thickness(flags):
+    """hfd_set_thickness rewrites the stored tensor in place (same address and
+    size), so a captured field graph computes the new geometry's field on
+    its next replay: the Newton loop of the thickness optimisation (Sec. 4)
+    re-uses one captured evaluation."""
+    import torch
+    wl = W.small_case(20, 16, 4, seed=73, batch=1)
+    plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=1, flags=flags)
+    m = torch.from_numpy(wl.m.astype(np.float32)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.field(m, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        h = plan.field(m, stream=s)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(74)
+    for r in range(3):
+        t_new = wl.thickness * rng.uniform(0.7, 1.3, wl.thickness.shape)
+        plan.set_thickness(t_new)          # contiguous stack from 0
+        g.replay()
+        torch.cuda.synchronize()
+        got = h.clone()
+        fresh = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, t_new, None, batch_max=1, flags=flags)
+        ref = fresh.field(m)
+        torch.cuda.synchronize()
+        fresh.destroy()
+        assert torch.equal(got, ref), f"replay {r} after set_thickness differs"
+    plan.destroy()
+
+
+def test_failed_set_thickness_keeps_the_plan_usable():
+    """A geometry rejected by validation leaves the stored tensor untouched."""
+    import torch
+    wl = W.small_case(10, 8, 3, seed=75, batch=1)
+    plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=1)
+    m = torch.from_numpy(wl.m.astype(np.float32)).cuda()
+    h0 = plan.field(m).clone()
+    bad = wl.thickness.copy()
+    bad[0, 1] = -1.0
+    with pytest.raises(hfd.HFDError) as ei:
+        plan.set_thickness(bad, wl.z_bottom)
+    assert ei.value.status == hfd.HFD_EINVAL
+    h1 = plan.field(m)
+    torch.cuda.synchronize()
+    assert torch.equal(h0, h1)
+    plan.destroy()
