@@ -7,7 +7,16 @@ in HBM.  Steps are replayed from a HIP graph that holds G complete evaluations
 (G: the largest divisor of K up to 10, or --graph-evals), so K steps are K / G
 replays.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph] [--graph-evals G]
+The line carries the roofline of the dominant kernel against the method's
+algorithmic bytes (m in, h out, the unique FP32 Fourier tensor once), the
+end-to-end fraction, per-evaluation median / p10 / p90 over many replays,
+a table of the other workloads (128^2 x 8, 512^2 x 4 with 64 states,
+256^2 x 32, 256^2 x 10 with 16 thickness candidates and its VJP), and the
+oracle timed on the host: the hybrid FFT of eq. FFT_v2 in numpy and the
+brute-force sum.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-configs] [--no-graph]
+                  [--graph-evals G]
 """
 from __future__ import annotations
 
@@ -23,7 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, public spec
-FP32_VALU_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
+FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X FP32 vector, public spec (packed FMA)
+FP32_VALU_NONPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (one FMA per lane)
+STATS_REPLAYS = 200             # replays behind the median / p10 / p90
 
 
 def parse():
@@ -33,6 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="M0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the table of the other workloads (C2, C3, C4, C5 and the C5 VJP)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--graph-evals", type=int, default=0,
                     help="evaluations captured per HIP graph (0: the largest divisor of --steps "
@@ -64,16 +77,28 @@ def graph_evals(steps: int, requested: int = 0) -> int:
     return G
 
 
-def algorithmic_bytes(nx, ny, nz, B, Lx, Ly):
-    """m in + h out (FP32) + the unique-pair Fourier tensor (5 FP32 components on
-    the (Lx/2+1) x (Ly/2+1) quadrant) read once."""
+def algorithmic_bytes(nx, ny, nz, B, G=1):
+    """Bytes the method must move per launch: m in and h out in FP32
+    (24 nx ny nz per state) plus the unique-pair Fourier tensor, six FP32
+    components on the (nx+1) x (ny+1) quadrant, read once per stack."""
     P = nz * (nz + 1) // 2
-    return B * 24 * nx * ny * nz + P * 5 * (Lx // 2 + 1) * (Ly // 2 + 1) * 4
+    return B * 24 * nx * ny * nz + G * 24 * (nx + 1) * (ny + 1) * P
+
+
+def algorithmic_flops(nx, ny, nz, B):
+    """FP32 flops per launch: the pruned 2D FFTs (5 N log2 N convention) of
+    the 3 nz input and output signals and the explicit layer sum, 36 nz^2
+    per frequency of the (nx+1) x 2ny half spectrum."""
+    Lx, Ly = 2 * nx, 2 * ny
+    fft = 3 * nz * 2 * (ny * 2.5 * Lx * np.log2(Lx) + (nx + 1) * 5 * Ly * np.log2(Ly))
+    mix = 36 * nz * nz * (nx + 1) * Ly
+    return B * (fft + mix)
 
 
 def fused_kernel_bytes(nx, ny, nz, B, Lx, Ly):
-    """Bytes the fused y-pass kernel must move: the x-pass spectra in and out
-    (complex64, Lx/2 columns of ny) plus the tensor quadrant."""
+    """Bytes the fused y-pass kernel itself moves: the x-pass spectra in and
+    out (complex64, Lx/2 columns of ny) plus the stored tensor quadrant (five
+    FP32 components; zz follows from the trace)."""
     P = nz * (nz + 1) // 2
     return 2 * B * 3 * nz * (Lx // 2) * ny * 8 + P * 5 * (Lx // 2 + 1) * (Ly // 2 + 1) * 4
 
@@ -105,7 +130,7 @@ def measured_traffic(workload):
                      float(kv["write_kb"]) * float(kv["write_factor"]))
 
 
-def cpu_baseline(wl, target_s=12.0):
+def cpu_baseline_bruteforce(wl, target_s=12.0):
     """The oracle's brute-force sum timed on a bounded sample of target cells of
     layer 0 (all sources of all layers), extrapolated to one full evaluation.
     Pair-table construction (the oracle's tensor setup) is timed apart and not
@@ -145,6 +170,38 @@ def cpu_baseline(wl, target_s=12.0):
                    f"cells of layer 0 against all {cells} source cells, {t_n2:.1f} s incl. "
                    f"{t_tab:.1f} s of pair tables for that layer; extrapolated to {cells} targets "
                    f"= {t_eval:.0f} s per evaluation (tables excluded)"),
+    }
+
+
+def cpu_baseline_hybrid(wl, target_s=10.0):
+    """The oracle's hybrid FFT (eq. FFT_v2: numpy 2D FFTs per layer, explicit
+    layer sum per frequency, inverse FFT, crop) on the full workload: the same
+    algorithm as the GPU path, FP64.  Its Fourier tensor (the oracle's pair
+    tables and their DFTs) is built first and timed apart, like the GPU's
+    tensor setup.  numpy's FFT and einsum run on one thread."""
+    import oracle
+    zb, t = wl.z_bottom[0], wl.thickness[0]
+    m = wl.m[0].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    Ntil = oracle.fourier_tensor(wl.nx, wl.ny, wl.dx, wl.dy, zb, t)
+    t_setup = time.perf_counter() - t0
+    n, t_run = 0, 0.0
+    while n < 1 or (t_run < target_s and n < 20):
+        t0 = time.perf_counter()
+        oracle.fft_field(wl.nx, wl.ny, wl.dx, wl.dy, zb, t, m, Ntil=Ntil)
+        t_run += time.perf_counter() - t0
+        n += 1
+    t_eval = t_run / n
+    return {
+        "value": 1.0 / t_eval,
+        "unit": "evals/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"hybrid FFT of eq. FFT_v2 in FP64 (numpy FFT and einsum, one thread) on the whole "
+                   f"{wl.nx}x{wl.ny}x{wl.nz} workload, {n} evaluation(s) in {t_run:.1f} s = "
+                   f"{t_eval:.2f} s each; its Fourier tensor (pair tables on {oracle.num_threads()} "
+                   f"threads + DFTs) took {t_setup:.1f} s and is not counted"),
+        "tensor_setup_s": t_setup,
     }
 
 
@@ -284,6 +341,100 @@ def time_vjp(wl, m, steps, warmup, stream):
     return res
 
 
+def percentiles(x):
+    x = np.asarray(x, dtype=np.float64)
+    return {"median": float(np.median(x)), "p10": float(np.percentile(x, 10)),
+            "p90": float(np.percentile(x, 90)), "n": int(x.size)}
+
+
+def replay_stats(graph, stream, per_replay, n):
+    """Per-evaluation times of n replays of `graph` (each holds `per_replay`
+    evaluations), measured with HIP events on the launch stream."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n)]
+    with torch.cuda.stream(stream):
+        for e0, e1 in evs:
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+    torch.cuda.synchronize()
+    return percentiles([e0.elapsed_time(e1) / per_replay for e0, e1 in evs])
+
+
+def roofline_of(stages, alg_bytes, alg_flops, ms_per_eval, kernel_bytes=None):
+    """HBM roofline of the dominant stage against the method's algorithmic
+    bytes, the end-to-end fraction, and the FP32 VALU fraction of the
+    algorithmic flops."""
+    dom = max(stages, key=stages.get)
+    dom_ms = stages[dom]
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    e2e = alg_bytes / (ms_per_eval * 1e-3) / 1e9
+    tf = alg_flops / (ms_per_eval * 1e-3) / 1e12
+    r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBPS, "kernel": dom, "kernel_ms": dom_ms,
+         "alg_bytes_per_launch": alg_bytes,
+         "end_to_end_GBps": e2e, "end_to_end_frac": e2e / HBM_PEAK_GBPS,
+         "valu_TFLOPs": tf, "valu_frac": tf / FP32_VALU_PEAK_TFLOPS,
+         "valu_frac_nonpacked": tf / FP32_VALU_NONPACKED_TFLOPS}
+    if kernel_bytes is not None:
+        kb = kernel_bytes / (dom_ms * 1e-3) / 1e9
+        r["kernel_own_bytes"] = kernel_bytes
+        r["kernel_frac"] = kb / HBM_PEAK_GBPS
+    return r
+
+
+def measure_config(name, steps, warmup, stream):
+    """One workload: autotuned field path, graph of 10 evaluations, per
+    evaluation median / p10 / p90 over 40 replays, stage durations, roofline
+    and error against the stored oracle samples."""
+    import torch
+    from paper_1910_07054_amd import hfd
+    from paper_1910_07054_amd import workloads as W
+    wl = W.CONFIGS[name]()
+    B, G = wl.batch, wl.n_geom
+    t0 = time.perf_counter()
+    plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=B)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    tune = plan.autotune(B)
+    m = torch.from_numpy(wl.m.astype(np.float32)).cuda()
+    h = torch.empty_like(m)
+    with torch.cuda.stream(stream):
+        for _ in range(max(warmup, 1)):
+            plan.field(m, out=h, stream=stream)
+    torch.cuda.synchronize()
+    ge = 10
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for _ in range(ge):
+            plan.field(m, out=h, stream=stream)
+    graph.replay()
+    torch.cuda.synchronize()
+    st = replay_stats(graph, stream, ge, 40)
+    stages = plan.time_stages(m, h, reps=20, stream=stream)
+    plan.field(m, out=h, stream=stream)
+    torch.cuda.synchronize()
+    err = golden_error(wl, h)
+    ms = st["median"]
+    inf = plan.info()
+    res = {"workload": f"{wl.nx}x{wl.ny}x{wl.nz}, {B} state(s), {G} stack(s)",
+           "evals_per_s": B / (ms * 1e-3), "ms_per_launch": st,
+           "cell_updates_per_s": B * wl.nx * wl.ny * wl.nz / (ms * 1e-3),
+           "path": tune.split("-> ")[-1], "stage_ms": stages, "setup_s": setup_s,
+           "err_vs_fp64_oracle": err,
+           "roofline": roofline_of(stages, algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, G),
+                                   algorithmic_flops(wl.nx, wl.ny, wl.nz, B), ms)}
+    if name == "C5":
+        res["vjp"] = time_vjp(wl, m, 10, 2, stream)
+    del graph
+    plan.destroy()
+    del m, h
+    torch.cuda.empty_cache()
+    print(f"config {name}: {res['evals_per_s']:.0f} evals/s, err {err}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -356,30 +507,26 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     evals_per_s = B / (elapsed / args.steps)
 
+    # distribution: STATS_REPLAYS replays of the same graph, HIP events on
+    # the launch stream, per evaluation
+    stats = replay_stats(graph, stream, G, STATS_REPLAYS) if graph is not None else None
+
     # per-stage kernel durations with HIP events on the launch stream (each
     # stage launched back to back; this leaves h overwritten, so the field is
     # evaluated once more for the accuracy check)
     stages = plan.time_stages(m, h, reps=max(args.steps, 10), stream=stream)
     plan.field(m, out=h, stream=stream)
     torch.cuda.synchronize()
-    dom = max(stages, key=stages.get)
-    if dom == "ymix_fused":
-        dom_bytes = fused_kernel_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly)
-    else:
-        dom_bytes = None
-    alg_bytes = algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly)
-
-    # accuracy against stored oracle values for this workload, if present
+    alg_bytes = algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, wl.n_geom)
+    alg_flops = algorithmic_flops(wl.nx, wl.ny, wl.nz, B)
     err = golden_error(wl, h)
 
-    roof = None
-    if dom_bytes is not None:
-        achieved = dom_bytes / (stages[dom] * 1e-3) / 1e9
-        traffic = measured_traffic(args.workload) if inf.Ly == 512 and wl.nz == 8 else None
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom,
-                "kernel_ms": stages[dom], "kernel_alg_bytes": dom_bytes,
-                "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)"}
+    dom = max(stages, key=stages.get)
+    kbytes = fused_kernel_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly) if dom == "ymix_fused" else None
+    roof = roofline_of(stages, alg_bytes, alg_flops, stats["median"] if stats else ms_per_step / B,
+                       kbytes)
+    roof["traffic"] = measured_traffic(args.workload) if dom == "ymix_fused" else None
+    roof["traffic_unit"] = "bytes per launch of the dominant kernel (copy-calibrated FETCH_SIZE + WRITE_SIZE)"
 
     out = {
         "metric": "demag field evals/s at 256^2 x 8 layers",
@@ -402,12 +549,19 @@ def main():
         "cell_updates_per_s": evals_per_s * wl.nx * wl.ny * wl.nz,
         "alg_GBps": alg_bytes / (elapsed / args.steps) / 1e9,
         "alg_bytes_per_eval": alg_bytes,
+        "ms_per_eval_stats": stats,
         "err_vs_fp64_oracle": err,
         "stage_ms": stages,
         "setup_ms": setup_ms,
         "autotune": tune,
         "roofline": roof,
     }
+    del graph
+    plan.destroy()
+    if not args.no_configs:
+        out["configs"] = {}
+        for name in ("C2", "C3", "C4", "C5"):
+            out["configs"][name] = measure_config(name, args.steps, args.warmup, stream)
     if args.compare:
         out["path_comparison"] = compare_paths(wl, m, args.steps, args.warmup, stream)
     if args.nz_sweep:
@@ -415,8 +569,9 @@ def main():
     if args.vjp:
         out["vjp"] = time_vjp(wl, m, max(args.steps // 4, 10), args.warmup, stream)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
-    plan.destroy()
+        cb = cpu_baseline_hybrid(wl)
+        cb["bruteforce"] = cpu_baseline_bruteforce(wl)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -22,24 +22,29 @@
 
 namespace hfd {
 
-template <typename R, int LX>
+// Rows are numbered flat over all signals (row r = signal r / ny, y = r % ny)
+// and a block takes TY consecutive rows, one wave or part of a wave per row.
+// TYO = 0 picks the default: 16 rows (or one per group of a 256-thread block),
+// halved until the tile fits in 80 KB of LDS.
+template <typename R, int LX, int TYO = 0>
 struct XPassShape {
     static constexpr int M = LX / 2;
     static constexpr int V = fft_vals(M);
     static constexpr int GT = M / V;
-    // 16 groups (one row each) per block where the block size allows
-    static constexpr int NT = GT * 16 < 256 ? 256 : (GT * 16 > 1024 ? 1024 : GT * 16);
-    static constexpr int NG = NT / GT;
     static constexpr int RS = M + 1;               // padded LDS row stride
-    // rows per block: at least 16 (or one per group), halved until the tile
-    // fits in 80 KB of LDS (two blocks per CU)
     static constexpr int pick_ty()
     {
-        int ty = NG > 16 ? NG : 16;
+        if (TYO > 0) return TYO;
+        const int ng = (GT * 16 < 256 ? 256 : (GT * 16 > 1024 ? 1024 : GT * 16)) / GT;
+        int ty = ng > 16 ? ng : 16;
         while (ty > 1 && sizeof(cpx<R>) * (size_t)ty * RS > 81920) ty /= 2;
         return ty;
     }
     static constexpr int TY = pick_ty();
+    // threads: one group per row, at least one wave, at most 1024
+    static constexpr int NT0 = GT * TY;
+    static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+    static constexpr int NG = NT / GT;
     static constexpr size_t LDS = sizeof(cpx<R>) * TY * RS;
     // waves per SIMD for two resident blocks (the register budget that allows it)
     static constexpr int WPE = NT / 128 > 8 ? 8 : (NT / 128 < 1 ? 1 : NT / 128);
@@ -134,30 +139,29 @@ struct RealSplit {
 // z[n] = x[2n] + i x[2n+1] followed by the even/odd split, which the row's
 // group applies to its own row.
 // ---------------------------------------------------------------------------
-template <typename R, int LX>
-__global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) void k_xfwd(const R* __restrict__ in, cpx<R>* __restrict__ out,
-                                              int nx, int ny, long long in_sig_stride,
-                                              int in_row_stride, const cpx<R>* __restrict__ twx)
+template <typename R, int LX, int TYO = 0>
+__global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TYO>::WPE)) void k_xfwd(
+    const R* __restrict__ in, cpx<R>* __restrict__ out, int nx, int ny, int nrows,
+    long long in_sig_stride, int in_row_stride, const cpx<R>* __restrict__ twx)
 {
-    using S = XPassShape<R, LX>;
+    using S = XPassShape<R, LX, TYO>;
     constexpr int M = S::M, GT = S::GT, NG = S::NG, TY = S::TY, RS = S::RS, NT = S::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int sig = blockIdx.y;
-    const int y0 = blockIdx.x * TY;
+    const int r0 = blockIdx.x * TY;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
-    const R* base = in + (long long)sig * in_sig_stride;
     Twiddles<R, M> tw;
     tw.load(g, twx, 2);
     RealSplit<R, LX> split;
     split.load(g, twx);
 
     for (int r = grp; r < TY; r += NG) {
-        const int y = y0 + r;
-        if (y >= ny) break;
+        const int fr = r0 + r;
+        if (fr >= nrows) break;
+        const int sig = fr / ny, y = fr - sig * ny;
         cpx<R>* row = sh + r * RS;
-        const R* src = base + (long long)y * in_row_stride;
-        if ((nx & 1) == 0 && (in_row_stride & 1) == 0) {
+        const R* src = in + (long long)sig * in_sig_stride + (long long)y * in_row_stride;
+        if ((nx & 1) == 0 && (in_row_stride & 1) == 0 && (in_sig_stride & 1) == 0) {
             // even rows: (x[2n], x[2n+1]) is one aligned 2-element load
             const cpx<R>* src2 = reinterpret_cast<const cpx<R>*>(src);
             const int nh = nx >> 1;
@@ -178,11 +182,14 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) 
         split.forward(row, g);
     }
     __syncthreads();
-    cpx<R>* dst = out + (long long)sig * M * ny;
+    // transposed store: consecutive threads take consecutive rows of one kx
     for (int idx = tid; idx < M * TY; idx += NT) {
         const int r = idx % TY, kx = idx / TY;
-        const int y = y0 + r;
-        if (y < ny) dst[(long long)kx * ny + y] = sh[r * RS + kx];
+        const int fr = r0 + r;
+        if (fr < nrows) {
+            const int sig = fr / ny, y = fr - sig * ny;
+            out[((long long)sig * M + kx) * ny + y] = sh[r * RS + kx];
+        }
     }
 }
 
@@ -190,38 +197,41 @@ __global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) 
 // x pass, inverse: packed half spectrum (transposed) -> nx reals per row.
 // Unnormalized; the 1/(Lx Ly) is folded into the tensor.
 // ---------------------------------------------------------------------------
-template <typename R, int LX>
-__global__ __launch_bounds__((XPassShape<R, LX>::NT), (XPassShape<R, LX>::WPE)) void k_xinv(const cpx<R>* __restrict__ in, R* __restrict__ out,
-                                              int nx, int ny, long long out_sig_stride,
-                                              int out_row_stride, const cpx<R>* __restrict__ twx)
+template <typename R, int LX, int TYO = 0>
+__global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TYO>::WPE)) void k_xinv(
+    const cpx<R>* __restrict__ in, R* __restrict__ out, int nx, int ny, int nrows,
+    long long out_sig_stride, int out_row_stride, const cpx<R>* __restrict__ twx)
 {
-    using S = XPassShape<R, LX>;
+    using S = XPassShape<R, LX, TYO>;
     constexpr int M = S::M, GT = S::GT, NG = S::NG, TY = S::TY, RS = S::RS, NT = S::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int sig = blockIdx.y;
-    const int y0 = blockIdx.x * TY;
+    const int r0 = blockIdx.x * TY;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
-    const cpx<R>* src = in + (long long)sig * M * ny;
     Twiddles<R, M> tw;
     tw.load(g, twx, 2);
     RealSplit<R, LX> split;
     split.load(g, twx);
     for (int idx = tid; idx < M * TY; idx += NT) {
         const int r = idx % TY, kx = idx / TY;
-        const int y = y0 + r;
-        sh[r * RS + kx] = (y < ny) ? src[(long long)kx * ny + y] : cpx<R>{R(0), R(0)};
+        const int fr = r0 + r;
+        cpx<R> v = {R(0), R(0)};
+        if (fr < nrows) {
+            const int sig = fr / ny, y = fr - sig * ny;
+            v = in[((long long)sig * M + kx) * ny + y];
+        }
+        sh[r * RS + kx] = v;
     }
     __syncthreads();
-    R* obase = out + (long long)sig * out_sig_stride;
     for (int r = grp; r < TY; r += NG) {
-        const int y = y0 + r;
-        if (y >= ny) break;
+        const int fr = r0 + r;
+        if (fr >= nrows) break;
+        const int sig = fr / ny, y = fr - sig * ny;
         cpx<R>* row = sh + r * RS;
         split.inverse(row, g);
         wave_sync();
-        R* dst = obase + (long long)y * out_row_stride;
-        if ((nx & 1) == 0 && (out_row_stride & 1) == 0) {
+        R* dst = out + (long long)sig * out_sig_stride + (long long)y * out_row_stride;
+        if ((nx & 1) == 0 && (out_row_stride & 1) == 0 && (out_sig_stride & 1) == 0) {
             cpx<R>* dst2 = reinterpret_cast<cpx<R>*>(dst);
             const int nh = nx >> 1;
             wave_fft<R, M, true>(

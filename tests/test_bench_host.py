@@ -4,6 +4,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -30,3 +31,22 @@ def test_graph_holds_a_divisor_of_the_steps(steps, requested, expect):
 def test_graph_evals_rejects_a_non_divisor(steps, requested):
     with pytest.raises(SystemExit):
         bench.graph_evals(steps, requested)
+
+
+def test_algorithmic_bytes_and_flops_per_launch():
+    """m in + h out in FP32 plus the unique six-component FP32 tensor on the
+    (nx+1)(ny+1) quadrant, once per stack: 69.65 MB for 256^2 x 8, 1.674 GB
+    for 64 states of 512^2 x 4, 102.9 MB per 256^2 x 10 candidate."""
+    assert bench.algorithmic_bytes(256, 256, 8, 1) == 24 * 256 * 256 * 8 + 24 * 257 * 257 * 36
+    assert abs(bench.algorithmic_bytes(256, 256, 8, 1) / 1e6 - 69.65) < 0.01
+    assert abs(bench.algorithmic_bytes(512, 512, 4, 64) / 1e9 - 1.674) < 0.001
+    assert abs(bench.algorithmic_bytes(256, 256, 10, 16, 16) / 16 / 1e6 - 102.9) < 0.1
+    # mixing: 36 nz^2 flops per frequency of the (nx+1) x 2ny half spectrum
+    f8 = bench.algorithmic_flops(256, 256, 8, 1)
+    f0 = bench.algorithmic_flops(256, 256, 8, 1) - 36 * 64 * 257 * 512
+    assert 0.7e9 < f8 < 0.76e9 and f0 > 0
+
+
+def test_percentiles():
+    p = bench.percentiles(np.arange(1, 101, dtype=float))
+    assert p["median"] == 50.5 and p["n"] == 100 and p["p10"] < p["median"] < p["p90"]

@@ -195,3 +195,29 @@ def test_autotune_keeps_results_correct():
         ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
         assert rel_err(h[b], ref) < 1e-5
     plan.destroy()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("nx,ny,nz", [(130, 13, 3), (60, 17, 2), (9, 33, 4)])
+def test_every_x_tile_matches_oracle(nx, ny, nz, fp64):
+    """The x passes with every compiled rows-per-block tile (flat row
+    numbering across signals; row counts that do not fill the last block)."""
+    wl = W.small_case(nx, ny, nz, seed=640 + nx, batch=2)
+    flags = hfd.HFD_FP64 if fp64 else hfd.HFD_FP32
+    plan = plan_for(wl, flags=flags)
+    refs = [oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0],
+                         wl.m[b].astype(np.float64 if fp64 else np.float32).astype(np.float64))
+            for b in range(2)]
+    tried = 0
+    for path in (0, 1):
+        for ty in (0, 4, 8, 16, 24, 32):
+            try:
+                plan.set_path(2, path, ty)
+            except hfd.HFDError:
+                continue
+            tried += 1
+            h, _ = run_field(plan, wl.m)
+            for b in range(2):
+                assert rel_err(h[b], refs[b]) < (1e-11 if fp64 else 1e-5), (path, ty, b)
+    assert tried >= 4
+    plan.destroy()
