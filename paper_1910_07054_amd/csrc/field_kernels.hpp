@@ -461,18 +461,20 @@ struct FusedShape {
 // packed again.  adjoint != 0 applies the transpose (inputs scaled by 1/t
 // instead of the outputs).
 // ---------------------------------------------------------------------------
+// Body of the fused y pass for column kx of state b (stack geom); the
+// kernels below launch it on a grid (M, states per stack, stacks).
 template <typename R, int LY, int NZMAX, bool ADJ>
-__global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
-    cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long q_geom_stride,
-    int QX, int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
+__device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __restrict__ X,
+                                            int ny, int nz, int M, const R* __restrict__ Q,
+                                            long long q_geom_stride, int QY,
+                                            const R* __restrict__ lp,
+                                            const cpx<R>* __restrict__ twy)
 {
     constexpr int NT = FusedShape<LY>::NT;
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int kx = blockIdx.x, b = blockIdx.y;
     const int S = 3 * nz;
-    const int geom = b / bpg;
     const long long sstride = (long long)M * ny;
     cpx<R>* col = X + ((long long)b * S * M + kx) * ny;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
@@ -610,6 +612,162 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
             [&](int pos, cpx<R> v) {
                 if (pos < ny) dst[pos] = v;
             });
+    }
+}
+
+// Grid (M, states per stack, stacks): the stack index is blockIdx.z, so no
+// integer division is needed (on gfx950 it runs on the vector unit, and a
+// buffer descriptor built from its result is treated as a per-lane value).
+template <typename R, int LY, int NZMAX, bool ADJ>
+__global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
+    cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long q_geom_stride,
+    int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
+{
+    const int geom = blockIdx.z;
+    ymix_column<R, LY, NZMAX, ADJ>(blockIdx.x, geom * bpg + blockIdx.y, geom, X, ny, nz, M, Q,
+                                   q_geom_stride, QY, lp, twy);
+}
+
+// ---------------------------------------------------------------------------
+// Fused y pass for a stack of exactly NZ layers (single precision, LY <= 512,
+// 512 threads): the same three phases as ymix_column, with every loop over
+// layers and layer pairs unrolled.  A lane's 3 NZ input values sit in
+// registers for the whole mixing, which walks the NZ (NZ + 1) / 2 stored pairs
+// in order (i, j >= i) and applies each block both ways; the tensor entries
+// are plain loads that the compiler schedules ahead of their use.  The column
+// spectra are read and written through buffer descriptors whose size is the
+// column's ny values: the zero padding of the forward transform and the crop
+// of the inverse come from the descriptor's range check.  Column 0 (the packed
+// kx = 0 and Lx/2 columns) runs ymix_column.
+// ---------------------------------------------------------------------------
+template <typename R, int LY, int NZ, bool ADJ>
+__global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
+    cpx<R>* __restrict__ X, int ny, int M, const R* __restrict__ Q, long long q_geom_stride,
+    int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
+{
+    constexpr int NT = FusedShape<LY>::NT;
+    constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
+    constexpr int S = 3 * NZ, P = NZ * (NZ + 1) / 2;
+    constexpr int NR = (S + NG - 1) / NG;  // signals per wave, at most
+    static_assert(sizeof(R) == 4 && NT == 512 && GT == 64, "single precision, 512-point columns");
+    const int kx = blockIdx.x, geom = blockIdx.z, b = geom * bpg + blockIdx.y;
+    if (kx == 0) {
+        ymix_column<R, LY, NZ, ADJ>(0, b, geom, X, ny, NZ, M, Q, q_geom_stride, QY, lp, twy);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
+    const long long sstride = (long long)M * ny;
+    cpx<R>* col = X + ((long long)b * S * M + kx) * ny;
+    const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+    const int cbytes = ny * (int)sizeof(cpx<R>);
+
+    // forward transforms: the inputs of all of this wave's signals are
+    // requested first, then transformed one after the other
+    {
+        Twiddles<R, LY> tw;
+        tw.load(g, twy, 1);
+        cpx<R> xin[NR][V];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
+            if (s < S) {
+                const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
+                fft_first_loads<R, LY>(xin[r], g, [&](int pos) -> cpx<R> {
+                    return __builtin_bit_cast(cpx<R>, __builtin_amdgcn_raw_buffer_load_b64(
+                                                          src, pos * (int)sizeof(cpx<R>), 0, 0));
+                });
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int s = grp + r * NG;
+            if (s < S) {
+                cpx<R>* reg = sh + s * LY;
+                wave_fft_pre<R, LY, false>(reg, g, tw, xin[r],
+                                           [&](int pos, cpx<R> v) { reg[pos] = v; });
+            }
+        }
+    }
+    __syncthreads();
+
+    // mixing: lanes 2t and 2t+1 take ky = t and LY - t (t = 0: 0 and LY/2),
+    // which share the quadrant tensor entry t
+    {
+        const int t = tid >> 1, p = tid & 1;
+        const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);
+        const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);
+        const long long colstride = (long long)P * 5 * QY;
+        const UniformBuf<R> qb(Q + (long long)geom * q_geom_stride + kx * colstride,
+                               (unsigned)(colstride * sizeof(R)));
+        const R* lpg = lp + (long long)geom * 2 * NZ;
+        const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
+        if (t < LY / 2) {
+            cpx<R> in[3][NZ], H[3][NZ];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int l = 0; l < NZ; ++l) {
+                    cpx<R> v = sh[(c * NZ + l) * LY + ky];
+                    if constexpr (ADJ) v = cscale(v, lpg[l]);  // T A T^-1: sources scaled by 1/t
+                    in[c][l] = v;
+                    H[c][l] = {R(0), R(0)};
+                }
+#pragma unroll
+            for (int i = 0; i < NZ; ++i)
+#pragma unroll
+                for (int j = i; j < NZ; ++j) {
+                    const int u = i * NZ - i * (i - 1) / 2 + (j - i);
+                    const R xx = qb.ld((unsigned)kq, (unsigned)((u * 5 + 0) * QY));
+                    const R yy = qb.ld((unsigned)kq, (unsigned)((u * 5 + 1) * QY));
+                    const R xy = sg * qb.ld((unsigned)kq, (unsigned)((u * 5 + 2) * QY));
+                    const R xz = qb.ld((unsigned)kq, (unsigned)((u * 5 + 3) * QY));
+                    const R yz = sg * qb.ld((unsigned)kq, (unsigned)((u * 5 + 4) * QY));
+                    R zz = -(xx + yy);
+                    if (i == j) {
+                        zz += lpg[NZ + i];
+                        block_apply(H[0][i], H[1][i], H[2][i], in[0][i], in[1][i], in[2][i], xx, yy,
+                                    zz, xy, xz, yz);
+                    } else {
+                        block_apply(H[0][i], H[1][i], H[2][i], in[0][j], in[1][j], in[2][j], xx, yy,
+                                    zz, xy, xz, yz);
+                        block_apply(H[0][j], H[1][j], H[2][j], in[0][i], in[1][i], in[2][i], xx, yy,
+                                    zz, xy, -xz, -yz);
+                    }
+                }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int l = 0; l < NZ; ++l) {
+                    cpx<R> v = H[c][l];
+                    if constexpr (!ADJ) v = cscale(v, lpg[l]);  // targets scaled by 1/t
+                    sh[(c * NZ + l) * LY + ky] = v;
+                }
+        }
+    }
+    __syncthreads();
+
+    // inverse transforms; stores beyond the column's ny values are dropped
+    {
+        Twiddles<R, LY> tw;
+        tw.load(g, twy, 1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
+            if (s < S) {
+                const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
+                cpx<R>* reg = sh + s * LY;
+                wave_fft<R, LY, true>(
+                    reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
+                    [&](int pos, cpx<R> v) {
+                        __builtin_amdgcn_raw_buffer_store_b64(
+                            __builtin_bit_cast(__attribute__((__vector_size__(8))) unsigned, v), dst,
+                            pos * (int)sizeof(cpx<R>), 0, 0);
+                    });
+            }
+        }
     }
 }
 

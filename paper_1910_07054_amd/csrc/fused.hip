@@ -1,4 +1,7 @@
-// Instances of the fused y-pass (y-DFT, z-mixing, inverse y-DFT in LDS).
+// Instances of the fused y-pass (y-DFT, z-mixing, inverse y-DFT in LDS):
+// the generic kernel (layer count up to NZMAX at run time); single-precision
+// 512-point columns of up to 10 layers go to the exact-layer-count kernels
+// (fused_exact_*.hip).
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -6,6 +9,7 @@ namespace hfd {
 
 namespace {
 constexpr size_t kMaxFusedLds = 163840;  // 160 KB of LDS per CU on gfx950
+constexpr int kMaxExactNz = 10;  // above, the accumulators spill
 
 // register budget: 1024-point columns run 16 waves per block (128 VGPRs),
 // which holds the accumulators of at most 4 layers
@@ -16,64 +20,71 @@ int nzmax_for(int nz, int LY)
     return nz <= 4 ? 4 : (nz <= 8 ? 8 : (nz <= 12 ? 12 : 0));
 }
 
+bool exact_nz_kernel(bool fp64, int LY, int nz) { return !fp64 && LY == 512 && nz >= 1 && nz <= kMaxExactNz; }
+
+hipError_t set_lds(const void* kernel, size_t lds)
+{
+    // the limit is raised once to the largest possible size
+    return lds > 65536 ? ensure_lds_limit(kernel, (int)kMaxFusedLds) : hipSuccess;
+}
+
 template <typename R, int LY, int NZMAX, bool ADJ>
-hipError_t fused_a(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
-                   int QY, const void* lp, int bpg, const void* tw, hipStream_t s)
+hipError_t fused_a(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+                   int QY, const void* lp, const void* tw, hipStream_t s)
 {
     const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
-    if (lds > 65536) {  // the limit is raised once to the largest possible size
-        hipError_t e = ensure_lds_limit((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>, 163840);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, B), dim3(FusedShape<LY>::NT), lds,
-                       s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QX, QY, (const R*)lp, bpg,
+    hipError_t e = set_lds((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, bpg, G), dim3(FusedShape<LY>::NT),
+                       lds, s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QY, (const R*)lp, bpg,
                        (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
 template <typename R, int LY, int NZMAX>
-hipError_t fused_t(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
-                   int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
+hipError_t fused_t(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+                   int QY, const void* lp, int adjoint, const void* tw, hipStream_t s)
 {
-    if (adjoint) return fused_a<R, LY, NZMAX, true>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, tw, s);
-    return fused_a<R, LY, NZMAX, false>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, tw, s);
+    if (adjoint) return fused_a<R, LY, NZMAX, true>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    return fused_a<R, LY, NZMAX, false>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
 }
 
 template <typename R, int LY>
-hipError_t fused_nz(int nz, void* X, int ny, int M, int B, const void* Q, long long qgs, int QX,
-                    int QY, const void* lp, int bpg, int adjoint, const void* tw, hipStream_t s)
+hipError_t fused_nz(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+                    int QY, const void* lp, int adjoint, const void* tw, hipStream_t s)
 {
     switch (nzmax_for<R>(nz, LY)) {
-    case 4: return fused_t<R, LY, 4>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 4: return fused_t<R, LY, 4>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
     case 8:
         if constexpr (sizeof(R) == 4 && LY < 1024)
-            return fused_t<R, LY, 8>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+            return fused_t<R, LY, 8>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
         return hipErrorInvalidValue;
     case 12:
         if constexpr (sizeof(R) == 4 && LY < 1024)
-            return fused_t<R, LY, 12>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+            return fused_t<R, LY, 12>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R>
-hipError_t fused_ly(int LY, int nz, void* X, int ny, int M, int B, const void* Q, long long qgs,
-                    int QX, int QY, const void* lp, int bpg, int adjoint, const void* tw,
+hipError_t fused_ly(int LY, int nz, void* X, int ny, int M, int bpg, int G, const void* Q,
+                    long long qgs, int QY, const void* lp, int adjoint, const void* tw,
                     hipStream_t s)
 {
     switch (LY) {
-    case 8: return fused_nz<R, 8>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 16: return fused_nz<R, 16>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 32: return fused_nz<R, 32>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 64: return fused_nz<R, 64>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 128: return fused_nz<R, 128>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 256: return fused_nz<R, 256>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 512: return fused_nz<R, 512>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
-    case 1024: return fused_nz<R, 1024>(nz, X, ny, M, B, Q, qgs, QX, QY, lp, bpg, adjoint, tw, s);
+    case 8: return fused_nz<R, 8>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 16: return fused_nz<R, 16>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 32: return fused_nz<R, 32>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 64: return fused_nz<R, 64>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 128: return fused_nz<R, 128>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 256: return fused_nz<R, 256>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 512: return fused_nz<R, 512>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 1024: return fused_nz<R, 1024>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
     default: return hipErrorInvalidValue;
     }
 }
+
 }  // namespace
 
 bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
@@ -89,10 +100,15 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
                         long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s)
 {
+    (void)QX;
     if (!fused_supported(fp64, LY, nz, nullptr)) return hipErrorInvalidValue;
+    if (bpg < 1 || B % bpg != 0) return hipErrorInvalidValue;
+    const int G = B / bpg;
+    if (exact_nz_kernel(fp64, LY, nz))
+        return launch_fused_exact(nz, adjoint, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, twy, s);
     if (fp64)
-        return fused_ly<double>(LY, nz, X, ny, M, B, Q, q_geom_stride, QX, QY, lp, bpg, adjoint, twy, s);
-    return fused_ly<float>(LY, nz, X, ny, M, B, Q, q_geom_stride, QX, QY, lp, bpg, adjoint, twy, s);
+        return fused_ly<double>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);
+    return fused_ly<float>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);
 }
 
 }  // namespace hfd

@@ -4,8 +4,9 @@
 // One FFT of length L is owned by a group of GT = L / V lanes of a single
 // 64-wide wavefront; every lane holds V complex values in registers.  Passes
 // use radix 8 (4 or 2 for the remainder).  Between passes the group exchanges
-// data through its own LDS region of L values; because the group never spans
-// two wavefronts, no workgroup barrier is needed inside a transform.
+// data through its own LDS region of L values (in a bank-spreading order, see
+// lds_swizzle); because the group never spans two wavefronts, no workgroup
+// barrier is needed inside a transform.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -126,6 +127,21 @@ __device__ __forceinline__ void dft(cpx<R>* v)
     else dft2<R, INV>(v);
 }
 
+// LDS slot of element `pos` in the intermediate passes of a transform.  The
+// writes of a radix-8 pass go to positions 8j + r (first pass) or
+// 64q + 8r + k (second pass) for the lanes j = 8q + k of a half-wave; stored
+// in natural order those land on 4 or 8 distinct 8-byte bank slots out of 32.
+// Xoring the low five bits of `pos` with a key built from the bits above
+// (bits 5-7 into bits 0-2, bits 6-7 into bits 3-4) spreads both patterns over
+// all 32 slots and leaves the unit-stride reads conflict-free.  The map is a
+// permutation of every aligned block of 32 positions, so a region of L
+// elements (L a power of two) stays a region of L elements.
+__device__ __forceinline__ int lds_swizzle(int pos)
+{
+    const int b = pos >> 5;
+    return pos ^ ((b & 7) | (((b >> 1) & 3) << 3));
+}
+
 // --- Stockham engine -------------------------------------------------------
 // X[k] = sum_n x[n] exp(-+2 pi i n k / L) (unnormalized in both directions).
 // Twiddles: table of exp(-2 pi i m / (L * tws)) read at index m * tws,
@@ -205,7 +221,7 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
             if constexpr (FIRST) {
                 if constexpr (!PRE) v[u * RAD + r] = load(pos);
             } else {
-                v[u * RAD + r] = sh[pos];
+                v[u * RAD + r] = sh[lds_swizzle(pos)];
             }
         }
     }
@@ -231,7 +247,7 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
         for (int r = 0; r < RAD; ++r) {
             const int pos = base + r * NS;
             if constexpr (LAST) store(pos, v[u * RAD + r]);
-            else sh[pos] = v[u * RAD + r];
+            else sh[lds_swizzle(pos)] = v[u * RAD + r];
         }
     }
     if constexpr (!LAST) {

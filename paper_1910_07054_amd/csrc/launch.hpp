@@ -37,6 +37,26 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
                         long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s);
 
+// exact-layer-count fused y pass (single precision, LY = 512, 1 <= nz <= 10):
+// grid (M, bpg, G); the three units cover 1-4, 5-7 and 8-10 layers
+hipError_t launch_fused_exact_1(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
+                                const void* Q, long long qgs, int QY, const void* lp,
+                                const void* tw, hipStream_t s);
+hipError_t launch_fused_exact_2(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
+                                const void* Q, long long qgs, int QY, const void* lp,
+                                const void* tw, hipStream_t s);
+hipError_t launch_fused_exact_3(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
+                                const void* Q, long long qgs, int QY, const void* lp,
+                                const void* tw, hipStream_t s);
+inline hipError_t launch_fused_exact(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
+                                     const void* Q, long long qgs, int QY, const void* lp,
+                                     const void* tw, hipStream_t s)
+{
+    if (nz <= 4) return launch_fused_exact_1(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    if (nz <= 7) return launch_fused_exact_2(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    return launch_fused_exact_3(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+}
+
 // generic mixing of the kx columns [kx0, kx0 + nkx)
 hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
                               const void* Q, long long q_geom_stride, int QX, int QY, const void* lp,
