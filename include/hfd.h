@@ -145,6 +145,22 @@ hfd_status hfd_set_thickness(hfd_plan plan, const double *thickness, const doubl
 hfd_status hfd_demag_field(hfd_plan plan, const void *m, void *h, int batch, void *stream);
 
 /*
+ * Same result as hfd_demag_field, for callers that cannot allocate device
+ * memory or use per-plan workspace (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the x-pass spectra live in a
+ * device scratch array of the library (32 MiB per GPU, held until the process
+ * ends) instead of the plan's workspace, and the call allocates nothing.
+ * It runs the fused y-pass: HFD_ENOTSUP for plans that cannot (HFD_EQUIDISTANT,
+ * HFD_SPLIT_PASSES, or a column that does not fit in LDS).  HFD_EINVAL when
+ * batch * 3 nz * (Lx/2) * ny complex values exceed the 32 MiB (e.g. more than
+ * two states of a 256 x 256 x 8 FP32 stack), plus the checks of
+ * hfd_demag_field.  Every call on one GPU shares that scratch: calls that
+ * overlap in time on the same GPU (other streams, other threads, other plans)
+ * race and must be serialized by the caller.
+ */
+hfd_status hfd_demag_field_noalloc(hfd_plan plan, const void *m, void *h, int batch, void *stream);
+
+/*
  * Vector-Jacobian product of h = h(m, t) for an upstream gradient grad_h.
  * The paper optimises a layer thickness by Newton's method on the mean field
  * in the free layer (Sec. 4) without saying how the derivative is formed;

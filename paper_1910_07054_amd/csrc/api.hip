@@ -40,9 +40,19 @@ hipError_t ensure_lds_limit(const void* kernel, int bytes)
 }
 }  // namespace hfd
 
+// Device scratch of hfd_demag_field_noalloc: the x-pass spectra of one call
+// (batch * 3 nz * (Lx/2) * ny complex values).  One copy per GPU, held until
+// the process ends; its device address is looked up once per device when the
+// first plan is created there (plan setup), never taken from the host-side name.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of `scratch` on that device
 
 hfd_status fail(hfd_status s, const std::string& msg)
 {
@@ -102,6 +112,26 @@ struct DeviceGuard {
         if (changed) (void)hipSetDevice(prev);
     }
 };
+
+// with the device current: record the address of `scratch` on it (once)
+hfd_status scratch_init(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(dev)) return HFD_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(HFD_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    return HFD_OK;
+}
+
+void* scratch_ptr(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const auto it = g_scratch_ptr.find(dev);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 }  // namespace
 
@@ -756,8 +786,9 @@ const char* path_name(int path)
 // `only` >= 0 launches the kernels of that stage alone (stage timing).
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
                      hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1,
-                     int only = -1, int xty = -1)
+                     int only = -1, int xty = -1, void* x1 = nullptr)
 {
+    if (!x1) x1 = p->X1;
     const int S = 3 * p->nz;
     const int nsig = batch * S;
     const int bpg = batch / p->G;
@@ -771,17 +802,17 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     };
     auto on = [&]() { return only < 0 || only == k; };
     if (on())
-        HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, p->X1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+        HFD_HIP(launch_xfwd(p->fp64, p->Lx, in, x1, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
                             nsig, p->twx, s, xty));
     mark();
     if (path == 0) {
         if (on())
-            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, batch, p->Q,
+            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, batch, p->Q,
                                  p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
         mark();
     } else {
         const long long ncols = (long long)nsig * p->M;
-        if (on()) HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
+        if (on()) HFD_HIP(launch_yfwd(p->fp64, p->Ly, x1, p->Mh, p->ny, ncols, p->twy, s));
         mark();
         if (on()) {
             if (path == 4) {
@@ -804,11 +835,11 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
             }
         }
         mark();
-        if (on()) HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, p->X1, p->ny, ncols, p->twy, s));
+        if (on()) HFD_HIP(launch_yinv(p->fp64, p->Ly, p->Hh, x1, p->ny, ncols, p->twy, s));
         mark();
     }
     if (on())
-        HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
+        HFD_HIP(launch_xinv(p->fp64, p->Lx, x1, out, p->nx, p->ny, (long long)p->ny * p->nx, p->nx,
                             nsig, p->twx, s, xty));
     mark();
     if (nstage) *nstage = k;
@@ -896,6 +927,8 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
 
     hipStream_t s = (hipStream_t)stream;
     if (hipGetDevice(&p->dev) != hipSuccess) { delete p; return fail(HFD_EHIP, "hipGetDevice failed"); }
+    st = scratch_init(p->dev);
+    if (st) { delete p; return st; }
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) == hipSuccess) {
         const long double need = (long double)q_elems * p->rsz + (long double)x1 + 2.0L * mh + (long double)bc;
@@ -988,6 +1021,24 @@ hfd_status hfd_demag_field(hfd_plan p, const void* m, void* h, int batch, void* 
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
     return run_field(p, m, h, batch, 0, (hipStream_t)stream);
+}
+
+hfd_status hfd_demag_field_noalloc(hfd_plan p, const void* m, void* h, int batch, void* stream)
+{
+    HFD_TRY(check_ready(p));
+    HFD_TRY(check_field_args(p, m, h, batch, "m", "h"));
+    if (p->eq3d || (p->flags & HFD_SPLIT_PASSES) || !fused_supported(p->fp64, p->Ly, p->nz, nullptr))
+        return fail(HFD_ENOTSUP, "hfd_demag_field_noalloc runs the fused y-pass, which this plan cannot use");
+    const long double need = (long double)batch * 3 * p->nz * p->M * (long double)p->ny * p->csz;
+    if (need > (long double)kScratchBytes)
+        return fail(HFD_EINVAL, "hfd_demag_field_noalloc: batch " + std::to_string(batch) + " needs " +
+                                    std::to_string((double)need) + " bytes of scratch, the limit is " +
+                                    std::to_string(kScratchBytes));
+    void* x1 = scratch_ptr(p->dev);
+    if (!x1) return fail(HFD_EHIP, "device scratch was not initialised for this device");
+    DeviceGuard dg;
+    HFD_HIP(dg.set(p->dev));
+    return run_field(p, m, h, batch, 0, (hipStream_t)stream, nullptr, nullptr, 0, -1, -1, x1);
 }
 
 hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* grad_m,

@@ -29,6 +29,7 @@ EXPORTS = (
     "hfd_setup_tensor", "hfd_set_thickness", "hfd_demag_field", "hfd_demag_vjp", "hfd_time_stages",
     "hfd_autotune", "hfd_get_info", "hfd_export_fourier_tensor", "hfd_export_real_tensor",
     "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error", "hfd_set_path",
+    "hfd_demag_field_noalloc",
 )
 
 
@@ -71,6 +72,7 @@ def load(path: str = LIB_PATH):
         "hfd_setup_tensor": [ctypes.POINTER(p), i, i, d, d, i, p, p, i, i, ctypes.c_uint, p],
         "hfd_set_thickness": [p, p, p, p],
         "hfd_demag_field": [p, p, p, i, p],
+        "hfd_demag_field_noalloc": [p, p, p, i, p],
         "hfd_demag_vjp": [p, p, p, p, p, i, p],
         "hfd_time_stages": [p, p, p, i, i, p, p, p, p, i],
         "hfd_autotune": [p, i, p, p, i],
@@ -208,6 +210,15 @@ class Plan:
         self.check(out, "out", B)
         _check(load().hfd_demag_field(self.handle, _dptr(m), _dptr(out), int(B),
                                       _stream_handle(stream)))
+        return out
+
+    def field_noalloc(self, m, out, stream=None):
+        """h = -N * m into `out` through hfd_demag_field_noalloc (the x-pass
+        spectra in the library's per-GPU device scratch; nothing allocated)."""
+        B = self.check(m, "m")
+        self.check(out, "out", B)
+        _check(load().hfd_demag_field_noalloc(self.handle, _dptr(m), _dptr(out), int(B),
+                                              _stream_handle(stream)))
         return out
 
     def vjp(self, m, grad_h, want_m: bool = True, want_t: bool = True, stream=None):
