@@ -184,6 +184,7 @@ struct hfd_plan_s {
     int path = 0;
     struct Tune {
         int path, xty;
+        int chunk;  // states per launch of the fused path (0: the whole batch)
     };
     std::map<int, Tune> tuned;
     // false while hfd_set_thickness rebuilds the plan and after it failed:
@@ -771,6 +772,25 @@ int xty_for(hfd_plan p, int batch)
     return best;
 }
 
+// Fused path, batch split into runs of `chunk` states launched one after the
+// other (x pass, y pass, inverse x pass per run), so that the x-pass spectra
+// of a run stay in the Infinity Cache between the three kernels.  A run lies
+// inside one stack or covers whole stacks.
+bool chunk_ok(hfd_plan p, int batch, int chunk)
+{
+    const int bpg = batch / p->G;
+    return chunk >= 1 && chunk <= batch && batch % chunk == 0 &&
+           (bpg % chunk == 0 || chunk % bpg == 0);
+}
+
+int chunk_for(hfd_plan p, int batch)
+{
+    auto it = p->tuned.find(batch);
+    if (it != p->tuned.end() && it->second.chunk > 0 && chunk_ok(p, batch, it->second.chunk))
+        return it->second.chunk;
+    return batch;
+}
+
 const char* path_name(int path)
 {
     switch (path) {
@@ -786,7 +806,7 @@ const char* path_name(int path)
 // `only` >= 0 launches the kernels of that stage alone (stage timing).
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
                      hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1,
-                     int only = -1, int xty = -1, void* x1 = nullptr)
+                     int only = -1, int xty = -1, void* x1 = nullptr, int chunk = -1)
 {
     if (!x1) x1 = p->X1;
     const int S = 3 * p->nz;
@@ -794,6 +814,28 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     const int bpg = batch / p->G;
     if (path < 0) path = path_for(p, batch);
     if (xty < 0) xty = xty_for(p, batch);
+    if (chunk < 0) chunk = chunk_for(p, batch);
+    if (path == 0 && chunk < batch && chunk_ok(p, batch, chunk) && !stage_ev && only < 0) {
+        // state-ordered runs of the fused path (see chunk_ok); one x-pass
+        // buffer of `chunk` states is reused by every run
+        const size_t state = (size_t)S * p->ny * p->nx * p->rsz;
+        for (int b0 = 0; b0 < batch; b0 += chunk) {
+            const int g0 = b0 / bpg;
+            const int bpg_c = bpg >= chunk ? chunk : bpg;
+            const char* in_c = (const char*)in + (size_t)b0 * state;
+            char* out_c = (char*)out + (size_t)b0 * state;
+            const char* q_c = (const char*)p->Q + (size_t)g0 * p->q_geom_stride * p->rsz;
+            const char* lp_c = (const char*)p->lp + (size_t)g0 * 2 * p->nz * p->rsz;
+            HFD_HIP(launch_xfwd(p->fp64, p->Lx, in_c, x1, p->nx, p->ny, (long long)p->ny * p->nx,
+                                p->nx, chunk * S, p->twx, s, xty));
+            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, chunk, q_c,
+                                 p->q_geom_stride, p->QX, p->QY, lp_c, bpg_c, adjoint, p->twy, s));
+            HFD_HIP(launch_xinv(p->fp64, p->Lx, x1, out_c, p->nx, p->ny, (long long)p->ny * p->nx,
+                                p->nx, chunk * S, p->twx, s, xty));
+        }
+        if (nstage) *nstage = 3;
+        return HFD_OK;
+    }
     if ((path == 2 || path == 3) && !mix_batched_supported(p->nz, batch, p->G)) path = 1;
     int k = 0;
     auto mark = [&]() {
@@ -1113,11 +1155,12 @@ hfd_status hfd_time_stages(hfd_plan p, const void* m, void* h, int batch, int re
     int ns = 0;
     // one full evaluation fills the intermediate buffers; then each stage's
     // kernels run `reps` times back to back between two events
-    hfd_status st = run_field(p, m, h, batch, 0, s, nullptr, &ns);
+    // (stages of the whole batch: a chunked configuration is timed unchunked)
+    hfd_status st = run_field(p, m, h, batch, 0, s, nullptr, &ns, -1, -1, -1, nullptr, batch);
     for (int k = 0; k < ns && st == HFD_OK; ++k) {
         (void)hipEventRecord(e0, s);
         for (int r = 0; r < reps && st == HFD_OK; ++r)
-            st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, -1, k);
+            st = run_field(p, m, h, batch, 0, s, nullptr, nullptr, -1, k, -1, nullptr, batch);
         (void)hipEventRecord(e1, s);
         if (st) break;
         if (hipEventSynchronize(e1) != hipSuccess) { st = fail(HFD_EHIP, "event sync failed"); break; }
@@ -1171,6 +1214,7 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     std::string rep = "batch=" + std::to_string(batch);
     int best = p->path;
     int best_ty = xty_for(p, batch);
+    int best_chunk = 0;
     double best_ms = 1e30;
     do {
         if (hipMemsetAsync(m, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
@@ -1179,14 +1223,14 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
             break;
         }
         // time one configuration: two warm-up evaluations, then 10 back to back
-        auto time_cfg = [&](int path, int xty, double& per) -> hfd_status {
+        auto time_cfg = [&](int path, int xty, int chunk, double& per) -> hfd_status {
             hfd_status t = HFD_OK;
             for (int w = 0; w < 2 && t == HFD_OK; ++w)
-                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty);
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk);
             const int reps = 10;
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < reps && t == HFD_OK; ++r)
-                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty);
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk);
             (void)hipEventRecord(e1, s);
             if (t) return t;
             if (hipEventSynchronize(e1) != hipSuccess) return fail(HFD_EHIP, "autotune sync failed");
@@ -1199,7 +1243,7 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
         const int xdef = xty_for(p, batch);
         for (int path : cand) {
             double per = 0;
-            st = time_cfg(path, xdef, per);
+            st = time_cfg(path, xdef, batch, per);
             if (st) break;
             char buf[96];
             std::snprintf(buf, sizeof buf, " %s=%.4fms", path_name(path), per);
@@ -1212,12 +1256,26 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
             for (int ty : {0, 4, 8, 16, 24, 32}) {
                 if (!x_tile_supported(p->fp64, p->Lx, ty) || ty == xdef) continue;
                 double per = 0;
-                st = time_cfg(best, ty, per);
+                st = time_cfg(best, ty, batch, per);
                 if (st) break;
                 char buf[64];
                 std::snprintf(buf, sizeof buf, " %d=%.4fms", ty, per);
                 rep += buf;
                 if (per < best_ms) { best_ms = per; best_ty = ty; }
+            }
+        }
+        // stage 3: states per run of the fused path (halving down to 1)
+        if (st == HFD_OK && best == 0 && batch > 1) {
+            rep += " | chunk:";
+            for (int c = batch / 2; c >= 1; c /= 2) {
+                if (!chunk_ok(p, batch, c)) continue;
+                double per = 0;
+                st = time_cfg(0, best_ty, c, per);
+                if (st) break;
+                char buf[64];
+                std::snprintf(buf, sizeof buf, " %d=%.4fms", c, per);
+                rep += buf;
+                if (per < best_ms) { best_ms = per; best_chunk = c; }
             }
         }
         (void)hipEventDestroy(e0);
@@ -1227,8 +1285,9 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     (void)hipFree(m);
     (void)hipFree(h);
     if (st) return st;
-    p->tuned[batch] = {best, best_ty};
+    p->tuned[batch] = {best, best_ty, best_chunk};
     rep += std::string(" -> ") + path_name(best) + " x" + std::to_string(best_ty);
+    if (best_chunk > 0) rep += " chunk" + std::to_string(best_chunk);
     if (report && report_len > 0) std::snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return HFD_OK;
 }
@@ -1253,6 +1312,22 @@ hfd_status hfd_set_path(hfd_plan p, int batch, int path, int x_tile)
         return fail(HFD_EINVAL, "x tile " + std::to_string(x_tile) + " is not compiled for Lx = " +
                                     std::to_string(p->Lx));
     p->tuned[batch] = {path, x_tile};
+    return HFD_OK;
+}
+
+hfd_status hfd_set_chunk(hfd_plan p, int batch, int chunk)
+{
+    HFD_TRY(check_plan(p));
+    if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
+    if (batch % p->G) return fail(HFD_EINVAL, "batch must be a multiple of n_geom");
+    if (chunk != 0 && !chunk_ok(p, batch, chunk))
+        return fail(HFD_EINVAL, "chunk must divide the batch and lie inside one stack or cover whole stacks");
+    auto it = p->tuned.find(batch);
+    if (it == p->tuned.end()) {
+        p->tuned[batch] = {p->path, xty_for(p, batch), chunk};
+    } else {
+        it->second.chunk = chunk;
+    }
     return HFD_OK;
 }
 

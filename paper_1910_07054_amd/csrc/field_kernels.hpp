@@ -629,8 +629,8 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
 }
 
 // ---------------------------------------------------------------------------
-// Fused y pass for a stack of exactly NZ layers (single precision, LY <= 512,
-// 512 threads): the same three phases as ymix_column, with every loop over
+// Fused y pass for a stack of exactly NZ layers (single precision, 512- or
+// 1024-point columns, 512 threads): the same three phases as ymix_column, with every loop over
 // layers and layer pairs unrolled.  A lane's 3 NZ input values sit in
 // registers for the whole mixing, which walks the NZ (NZ + 1) / 2 stored pairs
 // in order (i, j >= i) and applies each block both ways; the tensor entries
@@ -638,22 +638,35 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
 // spectra are read and written through buffer descriptors whose size is the
 // column's ny values: the zero padding of the forward transform and the crop
 // of the inverse come from the descriptor's range check.  Column 0 (the packed
-// kx = 0 and Lx/2 columns) runs ymix_column.
+// kx = 0 and Lx/2 columns) runs ymix_column (512-point columns) or a
+// separate k_ymix_fused launch (1024-point columns).
 // ---------------------------------------------------------------------------
-template <typename R, int LY, int NZ, bool ADJ>
-__global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
+template <int LY>
+struct ExactShape {
+    static constexpr int NT = 512;  // 8 waves at any column length: 256 VGPRs per lane
+};
+
+template <typename R, int LY, int NZ, bool ADJ, int PRE = 0>
+__global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
     cpx<R>* __restrict__ X, int ny, int M, const R* __restrict__ Q, long long q_geom_stride,
     int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
 {
-    constexpr int NT = FusedShape<LY>::NT;
+    constexpr int NT = ExactShape<LY>::NT;
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
     constexpr int S = 3 * NZ, P = NZ * (NZ + 1) / 2;
+    constexpr int TPL = LY / NT;           // frequency pairs per lane pair
     constexpr int NR = (S + NG - 1) / NG;  // signals per wave, at most
-    static_assert(sizeof(R) == 4 && NT == 512 && GT == 64, "single precision, 512-point columns");
-    const int kx = blockIdx.x, geom = blockIdx.z, b = geom * bpg + blockIdx.y;
-    if (kx == 0) {
-        ymix_column<R, LY, NZ, ADJ>(0, b, geom, X, ny, NZ, M, Q, q_geom_stride, QY, lp, twy);
-        return;
+    static_assert(sizeof(R) == 4 && GT == 64, "single precision, one transform per wavefront");
+    // 512-point columns: block 0 runs the packed column 0 with the generic
+    // body (one thread per frequency, as here); longer columns leave column 0
+    // to a separate launch of k_ymix_fused and start at kx = 1
+    constexpr bool OWN_COL0 = LY <= NT;
+    const int kx = blockIdx.x + (OWN_COL0 ? 0 : 1), geom = blockIdx.z, b = geom * bpg + blockIdx.y;
+    if constexpr (OWN_COL0) {
+        if (kx == 0) {
+            ymix_column<R, LY, NZ, ADJ>(0, b, geom, X, ny, NZ, M, Q, q_geom_stride, QY, lp, twy);
+            return;
+        }
     }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -661,6 +674,12 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
     cpx<R>* col = X + ((long long)b * S * M + kx) * ny;
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
     const int cbytes = ny * (int)sizeof(cpx<R>);
+    const int p = tid & 1;
+    const long long colstride = (long long)P * 5 * QY;
+    const UniformBuf<R> qb(Q + (long long)geom * q_geom_stride + kx * colstride,
+                           (unsigned)(colstride * sizeof(R)));
+    static_assert(PRE == 0 || TPL == 1, "tensor prefetch for one frequency pair per lane");
+    R qpre[PRE > 0 ? PRE : 1][5];
 
     // forward transforms: the inputs of all of this wave's signals are
     // requested first, then transformed one after the other
@@ -680,6 +699,15 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
                 });
             }
         }
+        // the first PRE tensor pairs are requested behind the column values
+        // (the wait counter is in order), to arrive while the transforms run
+        {
+            const int t = tid >> 1, kq = p == 0 ? t : (t == 0 ? LY / 2 : t);
+#pragma unroll
+            for (int u = 0; u < PRE; ++u)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) qpre[u][c] = qb.ld((unsigned)kq, (unsigned)((u * 5 + c) * QY));
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int s = grp + r * NG;
@@ -693,17 +721,13 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
     __syncthreads();
 
     // mixing: lanes 2t and 2t+1 take ky = t and LY - t (t = 0: 0 and LY/2),
-    // which share the quadrant tensor entry t
-    {
-        const int t = tid >> 1, p = tid & 1;
+    // which share the quadrant tensor entry t; t steps by NT / 2
+    const R* lpg = lp + (long long)geom * 2 * NZ;
+    for (int t = tid >> 1; t < LY / 2; t += NT / 2) {
         const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);
         const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);
-        const long long colstride = (long long)P * 5 * QY;
-        const UniformBuf<R> qb(Q + (long long)geom * q_geom_stride + kx * colstride,
-                               (unsigned)(colstride * sizeof(R)));
-        const R* lpg = lp + (long long)geom * 2 * NZ;
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
-        if (t < LY / 2) {
+        {
             cpx<R> in[3][NZ], H[3][NZ];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -719,11 +743,12 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused_nz(
 #pragma unroll
                 for (int j = i; j < NZ; ++j) {
                     const int u = i * NZ - i * (i - 1) / 2 + (j - i);
-                    const R xx = qb.ld((unsigned)kq, (unsigned)((u * 5 + 0) * QY));
-                    const R yy = qb.ld((unsigned)kq, (unsigned)((u * 5 + 1) * QY));
-                    const R xy = sg * qb.ld((unsigned)kq, (unsigned)((u * 5 + 2) * QY));
-                    const R xz = qb.ld((unsigned)kq, (unsigned)((u * 5 + 3) * QY));
-                    const R yz = sg * qb.ld((unsigned)kq, (unsigned)((u * 5 + 4) * QY));
+                    auto q = [&](int c) -> R {
+                        if constexpr (PRE > 0)
+                            if (u < PRE) return qpre[u < PRE ? u : 0][c];
+                        return qb.ld((unsigned)kq, (unsigned)((u * 5 + c) * QY));
+                    };
+                    const R xx = q(0), yy = q(1), xy = sg * q(2), xz = q(3), yz = sg * q(4);
                     R zz = -(xx + yy);
                     if (i == j) {
                         zz += lpg[NZ + i];

@@ -1,7 +1,7 @@
 // Instances of the fused y-pass (y-DFT, z-mixing, inverse y-DFT in LDS):
 // the generic kernel (layer count up to NZMAX at run time); single-precision
-// 512-point columns of up to 10 layers go to the exact-layer-count kernels
-// (fused_exact_*.hip).
+// 512-point columns of up to 10 layers and 1024-point columns of up to 4 go
+// to the exact-layer-count kernels (fused_exact_*.hip).
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -9,7 +9,6 @@ namespace hfd {
 
 namespace {
 constexpr size_t kMaxFusedLds = 163840;  // 160 KB of LDS per CU on gfx950
-constexpr int kMaxExactNz = 10;  // above, the accumulators spill
 
 // register budget: 1024-point columns run 16 waves per block (128 VGPRs),
 // which holds the accumulators of at most 4 layers
@@ -20,7 +19,7 @@ int nzmax_for(int nz, int LY)
     return nz <= 4 ? 4 : (nz <= 8 ? 8 : (nz <= 12 ? 12 : 0));
 }
 
-bool exact_nz_kernel(bool fp64, int LY, int nz) { return !fp64 && LY == 512 && nz >= 1 && nz <= kMaxExactNz; }
+
 
 hipError_t set_lds(const void* kernel, size_t lds)
 {
@@ -104,8 +103,8 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
     if (!fused_supported(fp64, LY, nz, nullptr)) return hipErrorInvalidValue;
     if (bpg < 1 || B % bpg != 0) return hipErrorInvalidValue;
     const int G = B / bpg;
-    if (exact_nz_kernel(fp64, LY, nz))
-        return launch_fused_exact(nz, adjoint, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, twy, s);
+    if (fused_exact_supported(fp64, LY, nz))
+        return launch_fused_exact(LY, nz, adjoint, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, twy, s);
     if (fp64)
         return fused_ly<double>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);
     return fused_ly<float>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);

@@ -1,4 +1,4 @@
-// Exact-layer-count fused y pass, 1 to 4 layers.
+// Exact-layer-count fused y pass, 512-point columns, 1 to 4 layers.
 #include "fused_exact.hpp"
 
 namespace hfd {
@@ -8,10 +8,10 @@ hipError_t launch_fused_exact_1(int nz, int adjoint, void* X, int ny, int M, int
                                    const void* tw, hipStream_t s)
 {
     switch (nz) {
-    case 1: return fused_exact_t<1>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 2: return fused_exact_t<2>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 3: return fused_exact_t<3>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 4: return fused_exact_t<4>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 1: return fused_exact_t<512, 1>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 2: return fused_exact_t<512, 2>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 3: return fused_exact_t<512, 3>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 4: return fused_exact_t<512, 4>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,4 +1,4 @@
-// Exact-layer-count fused y pass, 5 to 7 layers.
+// Exact-layer-count fused y pass, 512-point columns, 5 to 7 layers.
 #include "fused_exact.hpp"
 
 namespace hfd {
@@ -8,9 +8,9 @@ hipError_t launch_fused_exact_2(int nz, int adjoint, void* X, int ny, int M, int
                                    const void* tw, hipStream_t s)
 {
     switch (nz) {
-    case 5: return fused_exact_t<5>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 6: return fused_exact_t<6>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 7: return fused_exact_t<7>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 5: return fused_exact_t<512, 5>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 6: return fused_exact_t<512, 6>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 7: return fused_exact_t<512, 7>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,4 +1,4 @@
-// Exact-layer-count fused y pass, 8 to 10 layers.
+// Exact-layer-count fused y pass, 512-point columns, 8 to 10 layers.
 #include "fused_exact.hpp"
 
 namespace hfd {
@@ -8,9 +8,9 @@ hipError_t launch_fused_exact_3(int nz, int adjoint, void* X, int ny, int M, int
                                    const void* tw, hipStream_t s)
 {
     switch (nz) {
-    case 8: return fused_exact_t<8>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 9: return fused_exact_t<9>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 10: return fused_exact_t<10>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 8: return fused_exact_t<512, 8>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 9: return fused_exact_t<512, 9>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 10: return fused_exact_t<512, 10>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -221,3 +221,58 @@ def test_every_x_tile_matches_oracle(nx, ny, nz, fp64):
                 assert rel_err(h[b], refs[b]) < (1e-11 if fp64 else 1e-5), (path, ty, b)
     assert tried >= 4
     plan.destroy()
+
+
+# ---------------------------------------------------------------------------
+# Exact-layer-count fused kernel at 1024-point columns and state-ordered runs
+# of the fused path (hfd_set_chunk)
+# ---------------------------------------------------------------------------
+def test_exact_kernel_1024_point_columns_field_and_adjoint():
+    """ny in (256, 512] pads to Ly = 1024: columns 1.. by the exact-layer
+    kernel, the packed column 0 by the generic kernel; forward field and
+    transpose against the oracle."""
+    import torch
+    wl = W.small_case(10, 300, 4, seed=651, batch=2)
+    plan = plan_for(wl)
+    assert plan.info().Ly == 1024 and plan.info().fused
+    h, mused = run_field(plan, wl.m)
+    g = np.random.default_rng(652).standard_normal(wl.m.shape).astype(np.float32)
+    gm, _ = plan.vjp(None, torch.from_numpy(g).cuda(), want_m=True, want_t=False)
+    gm = gm.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
+        assert rel_err(h[b], ref) < 1e-5, b
+        reft = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0],
+                            g[b].astype(np.float64), transpose=True)
+        assert rel_err(gm[b], reft) < 1e-5, b
+    plan.destroy()
+
+
+@pytest.mark.parametrize("ny", [140, 300])
+def test_chunked_runs_match_oracle_with_two_stacks(ny):
+    """Batch of 6 states over 2 stacks (3 states each) evaluated in runs of 1,
+    3 and 6 states: every state against the oracle of its own stack; a run of
+    2 would straddle the stacks and is refused."""
+    import torch
+    nx, nz, B = 20, 3, 6
+    rng = np.random.default_rng(660 + ny)
+    t = rng.uniform(0.5, 2.5, (2, nz))
+    z = np.stack([np.concatenate([[0.0], np.cumsum(t[k, :-1] + rng.uniform(0.2, 0.8, nz - 1))])
+                  for k in range(2)])
+    m = rng.standard_normal((B, 3, nz, ny, nx))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    m32 = m.astype(np.float32)
+    plan = hfd.Plan(nx, ny, 2.0, 1.5, t, z, batch_max=B)
+    refs = [oracle.field(nx, ny, 2.0, 1.5, z[b // 3], t[b // 3], m32[b].astype(np.float64))
+            for b in range(B)]
+    with pytest.raises(hfd.HFDError):
+        plan.set_chunk(B, 2)
+    mt = torch.from_numpy(m32).cuda()
+    for chunk in (1, 3, 6, 0):
+        plan.set_chunk(B, chunk)
+        h = plan.field(mt)
+        torch.cuda.synchronize()
+        h = h.cpu().numpy().astype(np.float64)
+        for b in range(B):
+            assert rel_err(h[b], refs[b]) < 1e-5, (chunk, b)
+    plan.destroy()
