@@ -247,23 +247,31 @@ def compare_paths(wl, m, steps, warmup, stream):
     res = {}
     h = torch.empty_like(m)
     plan1 = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=1, flags=hfd.HFD_FP32)
+    tune1 = plan1.autotune(1)
 
     def single():
         for b in range(B):
             plan1.field(m[b:b + 1], out=h[b:b + 1], stream=stream)
     ms = replay_ms(single, max(steps // 4, 5), warmup, stream)
     res["single_state_fp32_fused"] = {"ms_per_batch": ms, "evals_per_s": B / (ms * 1e-3),
-                                      "err_vs_fp64_oracle": golden_error(wl, h)}
+                                      "err_vs_fp64_oracle": golden_error(wl, h), "autotune": tune1}
     plan1.destroy()
     variants = [("fused_fp32", hfd.HFD_FP32), ("five_pass_fp32", hfd.HFD_SPLIT_PASSES),
                 ("five_pass_batched_fp32", hfd.HFD_MIX_BATCHED_FP32),
                 ("five_pass_split_bf16_mfma", hfd.HFD_MIX_SPLIT_BF16)]
     for name, fl in variants:
         plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=B, flags=fl)
+        # each variant with its own tuned x tile (and, on the fused path, state
+        # runs and kernel); the path itself stays the one the flags select
+        tune = plan.autotune(B)
+        path = {hfd.HFD_FP32: 0, hfd.HFD_SPLIT_PASSES: 1, hfd.HFD_MIX_BATCHED_FP32: 2,
+                hfd.HFD_MIX_SPLIT_BF16: 3}[fl]
+        if f"-> {('fused', 'five_pass', 'five_pass_batched_fp32', 'five_pass_bf16_mfma')[path]} " not in tune + " ":
+            plan.set_path(B, path, int(tune.rsplit(" x", 1)[1].split()[0]))
         h.zero_()
         ms = replay_ms(lambda: plan.field(m, out=h, stream=stream), steps, warmup, stream)
         res[name] = {"ms_per_batch": ms, "evals_per_s": B / (ms * 1e-3),
-                     "err_vs_fp64_oracle": golden_error(wl, h),
+                     "err_vs_fp64_oracle": golden_error(wl, h), "autotune": tune,
                      "stage_ms": plan.time_stages(m, h, reps=max(steps // 4, 5), stream=stream)}
         plan.destroy()
     base = res["single_state_fp32_fused"]["ms_per_batch"]

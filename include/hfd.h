@@ -211,16 +211,21 @@ hfd_status hfd_autotune(hfd_plan plan, int batch, void *stream, char *report, in
  * HFD_EINVAL for a configuration the plan cannot run. */
 hfd_status hfd_set_path(hfd_plan plan, int batch, int path, int x_tile);
 
-/* Pin the number of states per run of the fused path for `batch` states
- * (chunk = 0: the whole batch in one run).  The fused path launches its three
- * kernels once per run of `chunk` consecutive states, reusing one x-pass
- * buffer of `chunk` states, so that between the kernels the spectra of a run
- * stay in the 256 MB Infinity Cache instead of travelling through HBM (the
- * batched form of the paper's evaluation, Sec. 3.1, ordered state by state).
- * chunk must divide batch and a run must lie inside one stack or cover whole
- * stacks (chunk divides batch / n_geom, or is a multiple of it); HFD_EINVAL
- * otherwise.  hfd_autotune chooses it by timing; host only. */
-hfd_status hfd_set_chunk(hfd_plan plan, int batch, int chunk);
+/* Pin how the fused path runs `batch` states (hfd_autotune chooses both by
+ * timing; host only):
+ *   chunk    states per run (0 = the whole batch in one run).  The fused path
+ *            launches its three kernels once per run of `chunk` consecutive
+ *            states, reusing one x-pass buffer of `chunk` states, so that
+ *            between the kernels the spectra of a run can stay in the 256 MB
+ *            Infinity Cache instead of travelling through HBM (the batched
+ *            evaluation of Sec. 3.1, ordered state by state).  chunk must
+ *            divide batch, and a run must lie inside one stack or cover whole
+ *            stacks (chunk divides batch / n_geom, or is a multiple of it).
+ *   generic  1: the y pass with the layer count read at run time even where a
+ *            kernel compiled for the exact layer count exists (FP32, 512- and
+ *            1024-point columns); 0: the exact kernel where it exists.
+ * HFD_EINVAL for other values. */
+hfd_status hfd_set_fused(hfd_plan plan, int batch, int chunk, int generic);
 
 /* Plan description (host). */
 typedef struct {

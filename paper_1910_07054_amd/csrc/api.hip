@@ -184,7 +184,8 @@ struct hfd_plan_s {
     int path = 0;
     struct Tune {
         int path, xty;
-        int chunk;  // states per launch of the fused path (0: the whole batch)
+        int chunk;    // states per launch of the fused path (0: the whole batch)
+        int generic;  // fused path: 1 = run-time layer-count kernel instead of the exact one
     };
     std::map<int, Tune> tuned;
     // false while hfd_set_thickness rebuilds the plan and after it failed:
@@ -783,6 +784,12 @@ bool chunk_ok(hfd_plan p, int batch, int chunk)
            (bpg % chunk == 0 || chunk % bpg == 0);
 }
 
+bool generic_for(hfd_plan p, int batch)
+{
+    auto it = p->tuned.find(batch);
+    return it != p->tuned.end() && it->second.generic;
+}
+
 int chunk_for(hfd_plan p, int batch)
 {
     auto it = p->tuned.find(batch);
@@ -806,8 +813,10 @@ const char* path_name(int path)
 // `only` >= 0 launches the kernels of that stage alone (stage timing).
 hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoint, hipStream_t s,
                      hipEvent_t* stage_ev = nullptr, int* nstage = nullptr, int path = -1,
-                     int only = -1, int xty = -1, void* x1 = nullptr, int chunk = -1)
+                     int only = -1, int xty = -1, void* x1 = nullptr, int chunk = -1,
+                     int generic = -1)
 {
+    const bool gen = generic < 0 ? generic_for(p, batch) : generic != 0;
     if (!x1) x1 = p->X1;
     const int S = 3 * p->nz;
     const int nsig = batch * S;
@@ -829,7 +838,8 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
             HFD_HIP(launch_xfwd(p->fp64, p->Lx, in_c, x1, p->nx, p->ny, (long long)p->ny * p->nx,
                                 p->nx, chunk * S, p->twx, s, xty));
             HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, chunk, q_c,
-                                 p->q_geom_stride, p->QX, p->QY, lp_c, bpg_c, adjoint, p->twy, s));
+                                 p->q_geom_stride, p->QX, p->QY, lp_c, bpg_c, adjoint, p->twy, s,
+                                 gen));
             HFD_HIP(launch_xinv(p->fp64, p->Lx, x1, out_c, p->nx, p->ny, (long long)p->ny * p->nx,
                                 p->nx, chunk * S, p->twx, s, xty));
         }
@@ -850,7 +860,8 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     if (path == 0) {
         if (on())
             HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, batch, p->Q,
-                                 p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s));
+                                 p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s,
+                                 gen));
         mark();
     } else {
         const long long ncols = (long long)nsig * p->M;
@@ -1214,7 +1225,7 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     std::string rep = "batch=" + std::to_string(batch);
     int best = p->path;
     int best_ty = xty_for(p, batch);
-    int best_chunk = 0;
+    int best_chunk = 0, best_gen = 0;
     double best_ms = 1e30;
     do {
         if (hipMemsetAsync(m, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
@@ -1223,14 +1234,14 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
             break;
         }
         // time one configuration: two warm-up evaluations, then 10 back to back
-        auto time_cfg = [&](int path, int xty, int chunk, double& per) -> hfd_status {
+        auto time_cfg = [&](int path, int xty, int chunk, double& per, int gen = 0) -> hfd_status {
             hfd_status t = HFD_OK;
             for (int w = 0; w < 2 && t == HFD_OK; ++w)
-                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk);
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk, gen);
             const int reps = 10;
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < reps && t == HFD_OK; ++r)
-                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk);
+                t = run_field(p, m, h, batch, 0, s, nullptr, nullptr, path, -1, xty, nullptr, chunk, gen);
             (void)hipEventRecord(e1, s);
             if (t) return t;
             if (hipEventSynchronize(e1) != hipSuccess) return fail(HFD_EHIP, "autotune sync failed");
@@ -1264,13 +1275,24 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
                 if (per < best_ms) { best_ms = per; best_ty = ty; }
             }
         }
-        // stage 3: states per run of the fused path (halving down to 1)
+        // stage 3: the run-time layer-count fused kernel where an exact one exists
+        if (st == HFD_OK && best == 0 && fused_exact_supported(p->fp64, p->Ly, p->nz)) {
+            double per = 0;
+            st = time_cfg(0, best_ty, batch, per, 1);
+            if (st == HFD_OK) {
+                char buf[64];
+                std::snprintf(buf, sizeof buf, " | generic fused=%.4fms", per);
+                rep += buf;
+                if (per < best_ms) { best_ms = per; best_gen = 1; }
+            }
+        }
+        // stage 4: states per run of the fused path (halving down to 1)
         if (st == HFD_OK && best == 0 && batch > 1) {
             rep += " | chunk:";
             for (int c = batch / 2; c >= 1; c /= 2) {
                 if (!chunk_ok(p, batch, c)) continue;
                 double per = 0;
-                st = time_cfg(0, best_ty, c, per);
+                st = time_cfg(0, best_ty, c, per, best_gen);
                 if (st) break;
                 char buf[64];
                 std::snprintf(buf, sizeof buf, " %d=%.4fms", c, per);
@@ -1285,8 +1307,9 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
     (void)hipFree(m);
     (void)hipFree(h);
     if (st) return st;
-    p->tuned[batch] = {best, best_ty, best_chunk};
+    p->tuned[batch] = {best, best_ty, best_chunk, best_gen};
     rep += std::string(" -> ") + path_name(best) + " x" + std::to_string(best_ty);
+    if (best_gen) rep += " generic";
     if (best_chunk > 0) rep += " chunk" + std::to_string(best_chunk);
     if (report && report_len > 0) std::snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return HFD_OK;
@@ -1315,18 +1338,20 @@ hfd_status hfd_set_path(hfd_plan p, int batch, int path, int x_tile)
     return HFD_OK;
 }
 
-hfd_status hfd_set_chunk(hfd_plan p, int batch, int chunk)
+hfd_status hfd_set_fused(hfd_plan p, int batch, int chunk, int generic)
 {
     HFD_TRY(check_plan(p));
     if (batch < 1 || batch > p->batch_max) return fail(HFD_EBATCH, "batch out of range");
     if (batch % p->G) return fail(HFD_EINVAL, "batch must be a multiple of n_geom");
     if (chunk != 0 && !chunk_ok(p, batch, chunk))
         return fail(HFD_EINVAL, "chunk must divide the batch and lie inside one stack or cover whole stacks");
+    if (generic != 0 && generic != 1) return fail(HFD_EINVAL, "generic must be 0 or 1");
     auto it = p->tuned.find(batch);
     if (it == p->tuned.end()) {
-        p->tuned[batch] = {p->path, xty_for(p, batch), chunk};
+        p->tuned[batch] = {p->path, xty_for(p, batch), chunk, generic};
     } else {
         it->second.chunk = chunk;
+        it->second.generic = generic;
     }
     return HFD_OK;
 }

@@ -97,13 +97,13 @@ bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
 
 hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
                         long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
-                        int adjoint, const void* twy, hipStream_t s)
+                        int adjoint, const void* twy, hipStream_t s, bool generic)
 {
     (void)QX;
     if (!fused_supported(fp64, LY, nz, nullptr)) return hipErrorInvalidValue;
     if (bpg < 1 || B % bpg != 0) return hipErrorInvalidValue;
     const int G = B / bpg;
-    if (fused_exact_supported(fp64, LY, nz))
+    if (!generic && fused_exact_supported(fp64, LY, nz))
         return launch_fused_exact(LY, nz, adjoint, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, twy, s);
     if (fp64)
         return fused_ly<double>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);

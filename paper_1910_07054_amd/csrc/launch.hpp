@@ -33,9 +33,11 @@ hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, 
 
 // fused y pass: does a compiled instance exist for (fp64, LY, nz) with lds bytes?
 bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes);
+// generic = true: the run-time layer-count kernel even where an exact-layer
+// kernel exists (the autotuner times both)
 hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
                         long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
-                        int adjoint, const void* twy, hipStream_t s);
+                        int adjoint, const void* twy, hipStream_t s, bool generic = false);
 
 // exact-layer-count fused y pass (single precision; LY = 512 with 1 <= nz <=
 // 10, LY = 1024 with 1 <= nz <= 4): grid (M, bpg, G); units 1-3 cover 1-4, 5-7

@@ -29,7 +29,7 @@ EXPORTS = (
     "hfd_setup_tensor", "hfd_set_thickness", "hfd_demag_field", "hfd_demag_vjp", "hfd_time_stages",
     "hfd_autotune", "hfd_get_info", "hfd_export_fourier_tensor", "hfd_export_real_tensor",
     "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error", "hfd_set_path",
-    "hfd_demag_field_noalloc", "hfd_set_chunk",
+    "hfd_demag_field_noalloc", "hfd_set_fused",
 )
 
 
@@ -77,7 +77,7 @@ def load(path: str = LIB_PATH):
         "hfd_time_stages": [p, p, p, i, i, p, p, p, p, i],
         "hfd_autotune": [p, i, p, p, i],
         "hfd_set_path": [p, i, i, i],
-        "hfd_set_chunk": [p, i, i],
+        "hfd_set_fused": [p, i, i, i],
         "hfd_get_info": [p, ctypes.POINTER(Info)],
         "hfd_export_fourier_tensor": [p, i, p, ll],
         "hfd_export_real_tensor": [p, i, i, i, p, p],
@@ -269,9 +269,10 @@ class Plan:
         """Pin the field path and x-pass tile for `batch` states (path < 0: unpin)."""
         _check(load().hfd_set_path(self.handle, int(batch), int(path), int(x_tile)))
 
-    def set_chunk(self, batch: int, chunk: int):
-        """Pin the states per run of the fused path for `batch` states (0: whole batch)."""
-        _check(load().hfd_set_chunk(self.handle, int(batch), int(chunk)))
+    def set_fused(self, batch: int, chunk: int = 0, generic: bool = False):
+        """Pin the fused path's states per run (0: whole batch) and kernel
+        variant (generic: run-time layer count) for `batch` states."""
+        _check(load().hfd_set_fused(self.handle, int(batch), int(chunk), int(bool(generic))))
 
     # -- inspection ----------------------------------------------------------
     def export_fourier_tensor(self, geom: int = 0) -> np.ndarray:

@@ -225,7 +225,7 @@ def test_every_x_tile_matches_oracle(nx, ny, nz, fp64):
 
 # ---------------------------------------------------------------------------
 # Exact-layer-count fused kernel at 1024-point columns and state-ordered runs
-# of the fused path (hfd_set_chunk)
+# of the fused path and the generic kernel variant (hfd_set_fused)
 # ---------------------------------------------------------------------------
 def test_exact_kernel_1024_point_columns_field_and_adjoint():
     """ny in (256, 512] pads to Ly = 1024: columns 1.. by the exact-layer
@@ -251,8 +251,9 @@ def test_exact_kernel_1024_point_columns_field_and_adjoint():
 @pytest.mark.parametrize("ny", [140, 300])
 def test_chunked_runs_match_oracle_with_two_stacks(ny):
     """Batch of 6 states over 2 stacks (3 states each) evaluated in runs of 1,
-    3 and 6 states: every state against the oracle of its own stack; a run of
-    2 would straddle the stacks and is refused."""
+    3 and 6 states, with the exact-layer and the generic y-pass kernels: every
+    state against the oracle of its own stack; a run of 2 would straddle the
+    stacks and is refused."""
     import torch
     nx, nz, B = 20, 3, 6
     rng = np.random.default_rng(660 + ny)
@@ -266,10 +267,10 @@ def test_chunked_runs_match_oracle_with_two_stacks(ny):
     refs = [oracle.field(nx, ny, 2.0, 1.5, z[b // 3], t[b // 3], m32[b].astype(np.float64))
             for b in range(B)]
     with pytest.raises(hfd.HFDError):
-        plan.set_chunk(B, 2)
+        plan.set_fused(B, 2)
     mt = torch.from_numpy(m32).cuda()
-    for chunk in (1, 3, 6, 0):
-        plan.set_chunk(B, chunk)
+    for chunk, generic in ((1, False), (3, True), (6, False), (0, True), (0, False)):
+        plan.set_fused(B, chunk, generic)
         h = plan.field(mt)
         torch.cuda.synchronize()
         h = h.cpu().numpy().astype(np.float64)
