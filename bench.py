@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--vjp", action="store_true",
                     help="also time hfd_demag_vjp (grad m and grad thickness) on the workload, with the "
                          "derivative tensors recomputed per call and stored")
+    ap.add_argument("--hysteresis", type=int, default=0, metavar="STEPS",
+                    help="also run the free-layer hysteresis loop of Sec. 4 with STEPS field steps "
+                         "(the paper uses 2000; L-BFGS relaxation per step on the library's energy "
+                         "and gradient) and report the switching field")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -278,6 +282,21 @@ def compare_paths(wl, m, steps, warmup, stream):
     for v in res.values():
         v["speedup_vs_single_state"] = base / v["ms_per_batch"]
     return res
+
+
+def run_hysteresis(steps):
+    """Sec. 4: hysteresis of the free layer of the optimised MRAM disk (64 x 64
+    cells, SAFM middle layer 3.4389 nm), field along z (tilted 1e-4 rad), loop
+    +2.5 T -> -2.5 T -> +2.5 T in `steps` steps, L-BFGS per step.  The paper
+    reports 1.51 T for 2000 steps."""
+    from paper_1910_07054_amd import micromag as mm
+    res = mm.mram_hysteresis(steps=steps, progress=max(steps // 8, 1))
+    ev = int(res["evaluations"].sum())
+    return {"steps": steps, "seconds": res["seconds"], "energy_evaluations": ev,
+            "ms_per_evaluation": res["seconds"] * 1e3 / max(ev, 1),
+            "lbfgs_iterations": int(res["iterations"].sum()),
+            "switching_T": res["switching_T"], "H_sw_T": res["H_sw_T"], "paper_H_sw_T": 1.51,
+            "macrospin_estimate": res["estimate"], "field_tilt_rad": mm.FIELD_TILT}
 
 
 def nz_sweep(steps, warmup, stream, nzs=(1, 2, 4, 8, 16, 32, 64)):
@@ -576,6 +595,8 @@ def main():
         out["nz_sweep"] = nz_sweep(max(args.steps // 4, 20), args.warmup, stream)
     if args.vjp:
         out["vjp"] = time_vjp(wl, m, max(args.steps // 4, 10), args.warmup, stream)
+    if args.hysteresis:
+        out["hysteresis"] = run_hysteresis(args.hysteresis)
     if not args.no_cpu_baseline:
         cb = cpu_baseline_hybrid(wl)
         cb["bruteforce"] = cpu_baseline_bruteforce(wl)

@@ -113,6 +113,15 @@ struct DeviceGuard {
     }
 };
 
+}  // namespace
+
+namespace hfd {
+// error reporting for the other translation units (hfd_last_error)
+hfd_status report_error(hfd_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace hfd
+
+namespace {
+
 // with the device current: record the address of `scratch` on it (once)
 hfd_status scratch_init(int dev)
 {

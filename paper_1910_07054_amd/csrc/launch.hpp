@@ -4,7 +4,14 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+
+#include "../../include/hfd.h"
+
 namespace hfd {
+
+// set the message returned by hfd_last_error (api.hip) and return s
+hfd_status report_error(hfd_status s, const std::string& msg);
 
 constexpr int kMinL = 8;
 constexpr int kMaxL = 4096;

@@ -24,12 +24,13 @@ HFD_EQUIDISTANT = 32
 STATUS_NAMES = {0: "HFD_OK", -1: "HFD_EINVAL", -2: "HFD_ENOMEM", -3: "HFD_EHIP", -4: "HFD_EBATCH",
                 -5: "HFD_EHANDLE", -6: "HFD_ENOTSUP"}
 
-# every function declared in include/hfd.h
+# every function declared in include/hfd.h and include/hfd_mm.h
 EXPORTS = (
     "hfd_setup_tensor", "hfd_set_thickness", "hfd_demag_field", "hfd_demag_vjp", "hfd_time_stages",
     "hfd_autotune", "hfd_get_info", "hfd_export_fourier_tensor", "hfd_export_real_tensor",
     "hfd_forward_spectrum", "hfd_destroy", "hfd_last_error", "hfd_set_path",
     "hfd_demag_field_noalloc", "hfd_set_fused",
+    "hfd_mm_create", "hfd_mm_set_bias", "hfd_mm_energy_grad", "hfd_mm_destroy",
 )
 
 
@@ -78,6 +79,10 @@ def load(path: str = LIB_PATH):
         "hfd_autotune": [p, i, p, p, i],
         "hfd_set_path": [p, i, i, i],
         "hfd_set_fused": [p, i, i, i],
+        "hfd_mm_create": [ctypes.POINTER(p), p, p, d, d, d, p],
+        "hfd_mm_set_bias": [p, p, p],
+        "hfd_mm_energy_grad": [p, p, p, p, p, p, p, p],
+        "hfd_mm_destroy": [p],
         "hfd_get_info": [p, ctypes.POINTER(Info)],
         "hfd_export_fourier_tensor": [p, i, p, ll],
         "hfd_export_real_tensor": [p, i, i, i, p, p],
