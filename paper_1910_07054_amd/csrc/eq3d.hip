@@ -91,7 +91,7 @@ struct ZPassShape {
     static constexpr int V = fft_vals(LZ), GT = LZ / V;
     static constexpr int NT = 256, NG = NT / GT;
     // ky points per block: the tile holds 3 transforms of LZ values per point
-    static constexpr int TP = (sizeof(cpx<R>) * 3 * 16 * LZ <= 49152) ? 16 : 8;
+    static constexpr int TP = (sizeof(cpx<R>) * 3 * 16 * fft_region(LZ) <= 49152) ? 16 : 8;
 };
 
 // z pass: block = TP consecutive ky of one kx column (kx = M is the split-off
@@ -107,7 +107,8 @@ __global__ __launch_bounds__(256) void k_zpass3(const cpx<R>* __restrict__ Mh, c
 {
     using SH = ZPassShape<R, LZ>;
     constexpr int TP = SH::TP, GT = SH::GT, NG = SH::NG, NT = SH::NT, LZH = LZ / 2 + 1;
-    __shared__ cpx<R> sh[3 * TP * LZ];
+    constexpr int LZP = fft_region(LZ);  // LDS slots per transform
+    __shared__ cpx<R> sh[3 * TP * LZP];
     const int kx = blockIdx.y, b = blockIdx.z;
     const int ky0 = blockIdx.x * TP;
     const int S = 3 * nz;
@@ -119,17 +120,17 @@ __global__ __launch_bounds__(256) void k_zpass3(const cpx<R>* __restrict__ Mh, c
     Twiddles<R, LZ> tw;
     tw.load(g, twz, 1);
 
-    // stage: sh[(p * 3 + c) * LZ + l], zero for l >= nz
+    // stage: sh[(p * 3 + c) * LZP + l], zero for l >= nz
     for (int idx = tid; idx < TP * 3 * LZ; idx += NT) {
         const int p = idx % TP, r = idx / TP, c = r / LZ, l = r - c * LZ;
         const int ky = ky0 + p;
         cpx<R> v = {R(0), R(0)};
         if (l < nz && ky < LY) v = src[((long long)b * S + c * nz + l) * sstride + ky];
-        sh[(p * 3 + c) * LZ + l] = v;
+        sh[(p * 3 + c) * LZP + l] = v;
     }
     __syncthreads();
     for (int tr = grp; tr < 3 * TP; tr += NG) {
-        cpx<R>* reg = sh + tr * LZ;
+        cpx<R>* reg = sh + tr * LZP;
         wave_fft<R, LZ, false>(reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
                                [&](int pos, cpx<R> v) { reg[pos] = v; });
     }
@@ -147,15 +148,15 @@ __global__ __launch_bounds__(256) void k_zpass3(const cpx<R>* __restrict__ Mh, c
         const R* t = Tk + (long long)kzq * 6 * QY + kyq;
         const R xx = t[0], yy = t[QY], zz = t[2 * QY], xy = sy * t[3 * QY], xz = sz * t[4 * QY],
                 yz = sy * sz * t[5 * QY];
-        cpx<R>* v = sh + p * 3 * LZ + kz;
-        const cpx<R> X = v[0], Y = v[LZ], Z = v[2 * LZ];
+        cpx<R>* v = sh + p * 3 * LZP + kz;
+        const cpx<R> X = v[0], Y = v[LZP], Z = v[2 * LZP];
         v[0] = {xx * X.x + xy * Y.x + xz * Z.x, xx * X.y + xy * Y.y + xz * Z.y};
-        v[LZ] = {xy * X.x + yy * Y.x + yz * Z.x, xy * X.y + yy * Y.y + yz * Z.y};
-        v[2 * LZ] = {xz * X.x + yz * Y.x + zz * Z.x, xz * X.y + yz * Y.y + zz * Z.y};
+        v[LZP] = {xy * X.x + yy * Y.x + yz * Z.x, xy * X.y + yy * Y.y + yz * Z.y};
+        v[2 * LZP] = {xz * X.x + yz * Y.x + zz * Z.x, xz * X.y + yz * Y.y + zz * Z.y};
     }
     __syncthreads();
     for (int tr = grp; tr < 3 * TP; tr += NG) {
-        cpx<R>* reg = sh + tr * LZ;
+        cpx<R>* reg = sh + tr * LZP;
         wave_fft<R, LZ, true>(reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
                               [&](int pos, cpx<R> v) { reg[pos] = v; });
     }
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void k_zpass3(const cpx<R>* __restrict__ Mh, c
     for (int idx = tid; idx < TP * 3 * nz; idx += NT) {
         const int p = idx % TP, cl = idx / TP, c = cl / nz, l = cl - c * nz;
         const int ky = ky0 + p;
-        if (ky < LY) dst[((long long)b * S + cl) * sstride + ky] = sh[(p * 3 + c) * LZ + l];
+        if (ky < LY) dst[((long long)b * S + cl) * sstride + ky] = sh[(p * 3 + c) * LZP + l];
     }
 }
 

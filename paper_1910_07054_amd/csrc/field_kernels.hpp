@@ -31,7 +31,7 @@ struct XPassShape {
     static constexpr int M = LX / 2;
     static constexpr int V = fft_vals(M);
     static constexpr int GT = M / V;
-    static constexpr int RS = M + 1;               // padded LDS row stride
+    static constexpr int RS = fft_region(M) | 1;   // LDS row stride: a transform's region, odd
     static constexpr int pick_ty()
     {
         if (TYO > 0) return TYO;
@@ -137,9 +137,11 @@ struct RealSplit {
 // spectrum of LX/2 complex values, written transposed (y fastest).
 // A length-LX real transform is one complex transform of length LX/2 on
 // z[n] = x[2n] + i x[2n+1] followed by the even/odd split, which the row's
-// group applies to its own row.
+// group applies to its own row.  HALF: nx <= LX/2, so z[n] is zero for
+// n >= LX/4 and the first radix pass skips that half (the field path; the
+// tensor transforms run on full rows).
 // ---------------------------------------------------------------------------
-template <typename R, int LX, int TYO = 0>
+template <typename R, int LX, int TYO = 0, bool HALF = true>
 __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TYO>::WPE)) void k_xfwd(
     const R* __restrict__ in, cpx<R>* __restrict__ out, int nx, int ny, int nrows,
     long long in_sig_stride, int in_row_stride, const cpx<R>* __restrict__ twx)
@@ -165,12 +167,12 @@ __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TY
             // even rows: (x[2n], x[2n+1]) is one aligned 2-element load
             const cpx<R>* src2 = reinterpret_cast<const cpx<R>*>(src);
             const int nh = nx >> 1;
-            wave_fft<R, M, false>(
+            wave_fft<R, M, false, HALF>(
                 row, g, tw,
                 [&](int pos) -> cpx<R> { return pos < nh ? src2[pos] : cpx<R>{R(0), R(0)}; },
                 [&](int pos, cpx<R> v) { row[pos] = v; });
         } else {
-            wave_fft<R, M, false>(
+            wave_fft<R, M, false, HALF>(
                 row, g, tw,
                 [&](int pos) -> cpx<R> {
                     const int n0 = 2 * pos;
@@ -195,9 +197,10 @@ __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TY
 
 // ---------------------------------------------------------------------------
 // x pass, inverse: packed half spectrum (transposed) -> nx reals per row.
-// Unnormalized; the 1/(Lx Ly) is folded into the tensor.
+// Unnormalized; the 1/(Lx Ly) is folded into the tensor.  HALF: nx <= LX/2,
+// only the first half of the transform is kept.
 // ---------------------------------------------------------------------------
-template <typename R, int LX, int TYO = 0>
+template <typename R, int LX, int TYO = 0, bool HALF = true>
 __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TYO>::WPE)) void k_xinv(
     const cpx<R>* __restrict__ in, R* __restrict__ out, int nx, int ny, int nrows,
     long long out_sig_stride, int out_row_stride, const cpx<R>* __restrict__ twx)
@@ -234,13 +237,13 @@ __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TY
         if ((nx & 1) == 0 && (out_row_stride & 1) == 0 && (out_sig_stride & 1) == 0) {
             cpx<R>* dst2 = reinterpret_cast<cpx<R>*>(dst);
             const int nh = nx >> 1;
-            wave_fft<R, M, true>(
+            wave_fft<R, M, true, false, HALF>(
                 row, g, tw, [&](int pos) -> cpx<R> { return row[pos]; },
                 [&](int pos, cpx<R> v) {
                     if (pos < nh) dst2[pos] = v;
                 });
         } else {
-            wave_fft<R, M, true>(
+            wave_fft<R, M, true, false, HALF>(
                 row, g, tw, [&](int pos) -> cpx<R> { return row[pos]; },
                 [&](int pos, cpx<R> v) {
                     const int n0 = 2 * pos;
@@ -415,7 +418,7 @@ struct MirrorPoints {
             const int jj = j < nz ? j : 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const cpx<R> z = sh[(c * nz + jj) * LY + kp];
+                const cpx<R> z = sh[(c * nz + jj) * fft_region(LY) + kp];
                 R x = part ? z.y : z.x;
                 if constexpr (ADJ) x *= lpg[jj];
                 v[c][j] = (act && j < nz) ? x : R(0);
@@ -440,7 +443,7 @@ struct MirrorPoints {
             const R sc = ADJ ? R(1) : lpg[i];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                reinterpret_cast<R*>(&sh[(c * nz + i) * LY + kp])[part] = acc[c] * sc;
+                reinterpret_cast<R*>(&sh[(c * nz + i) * fft_region(LY) + kp])[part] = acc[c] * sc;
         }
     }
 };
@@ -472,6 +475,7 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
 {
     constexpr int NT = FusedShape<LY>::NT;
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
+    constexpr int LYP = fft_region(LY);  // LDS slots per signal
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
     const int S = 3 * nz;
@@ -517,7 +521,7 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
         const int s = grp + r * NG;
         if (s < S) {
             const cpx<R>* src = col + s * sstride;
-            fft_first_loads<R, LY>(xin[r], g, [&](int pos) -> cpx<R> {
+            fft_first_loads<R, LY, true>(xin[r], g, [&](int pos) -> cpx<R> {
                 return pos < ny ? src[pos] : cpx<R>{R(0), R(0)};
             });
         }
@@ -526,8 +530,8 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
     for (int r = 0; r < NR; ++r) {
         const int s = grp + r * NG;
         if (s < S) {
-            cpx<R>* reg = sh + s * LY;
-            wave_fft_pre<R, LY, false>(reg, g, tw, xin[r], [&](int pos, cpx<R> v) { reg[pos] = v; });
+            cpx<R>* reg = sh + s * LYP;
+            wave_fft_pre<R, LY, false, true>(reg, g, tw, xin[r], [&](int pos, cpx<R> v) { reg[pos] = v; });
         }
     }
     __syncthreads();
@@ -560,11 +564,11 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
                     if (l < nz) {
                         cpx<R> v = H[c * NZMAX + l];
                         if constexpr (!ADJ) v = cscale(v, invt[l]);
-                        sh[(c * nz + l) * LY + ky] = v;
+                        sh[(c * nz + l) * LYP + ky] = v;
                     }
         };
         auto ld = [&](int c, int l, int k) -> cpx<R> {
-            cpx<R> v = sh[(c * nz + l) * LY + k];
+            cpx<R> v = sh[(c * nz + l) * LYP + k];
             if constexpr (ADJ) v = cscale(v, isc(l));
             return v;
         };
@@ -606,8 +610,8 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
 
     for (int s = grp; s < S; s += NG) {
         cpx<R>* dst = col + s * sstride;
-        cpx<R>* reg = sh + s * LY;
-        wave_fft<R, LY, true>(
+        cpx<R>* reg = sh + s * LYP;
+        wave_fft<R, LY, true, false, true>(
             reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
             [&](int pos, cpx<R> v) {
                 if (pos < ny) dst[pos] = v;
@@ -655,6 +659,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
     constexpr int S = 3 * NZ, P = NZ * (NZ + 1) / 2;
     constexpr int TPL = LY / NT;           // frequency pairs per lane pair
+    constexpr int LYP = fft_region(LY);    // LDS slots per signal
     constexpr int NR = (S + NG - 1) / NG;  // signals per wave, at most
     static_assert(sizeof(R) == 4 && GT == 64, "single precision, one transform per wavefront");
     // 512-point columns: block 0 runs the packed column 0 with the generic
@@ -693,7 +698,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
             if (s < S) {
                 const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
                     (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
-                fft_first_loads<R, LY>(xin[r], g, [&](int pos) -> cpx<R> {
+                fft_first_loads<R, LY, true>(xin[r], g, [&](int pos) -> cpx<R> {
                     return __builtin_bit_cast(cpx<R>, __builtin_amdgcn_raw_buffer_load_b64(
                                                           src, pos * (int)sizeof(cpx<R>), 0, 0));
                 });
@@ -712,8 +717,8 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
         for (int r = 0; r < NR; ++r) {
             const int s = grp + r * NG;
             if (s < S) {
-                cpx<R>* reg = sh + s * LY;
-                wave_fft_pre<R, LY, false>(reg, g, tw, xin[r],
+                cpx<R>* reg = sh + s * LYP;
+                wave_fft_pre<R, LY, false, true>(reg, g, tw, xin[r],
                                            [&](int pos, cpx<R> v) { reg[pos] = v; });
             }
         }
@@ -733,7 +738,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int l = 0; l < NZ; ++l) {
-                    cpx<R> v = sh[(c * NZ + l) * LY + ky];
+                    cpx<R> v = sh[(c * NZ + l) * LYP + ky];
                     if constexpr (ADJ) v = cscale(v, lpg[l]);  // T A T^-1: sources scaled by 1/t
                     in[c][l] = v;
                     H[c][l] = {R(0), R(0)};
@@ -767,7 +772,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
                 for (int l = 0; l < NZ; ++l) {
                     cpx<R> v = H[c][l];
                     if constexpr (!ADJ) v = cscale(v, lpg[l]);  // targets scaled by 1/t
-                    sh[(c * NZ + l) * LY + ky] = v;
+                    sh[(c * NZ + l) * LYP + ky] = v;
                 }
         }
     }
@@ -783,8 +788,8 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
             if (s < S) {
                 const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
                     (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
-                cpx<R>* reg = sh + s * LY;
-                wave_fft<R, LY, true>(
+                cpx<R>* reg = sh + s * LYP;
+                wave_fft<R, LY, true, false, true>(
                     reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
                     [&](int pos, cpx<R> v) {
                         __builtin_amdgcn_raw_buffer_store_b64(
@@ -804,47 +809,49 @@ struct YPassShape {
     static constexpr int V = fft_vals(LY);
     static constexpr int GT = LY / V;
     static constexpr int NG0 = 256 / GT;
-    static constexpr int NGL = (int)(65536 / (sizeof(cpx<R>) * LY));
+    static constexpr int NGL = (int)(65536 / (sizeof(cpx<R>) * fft_region(LY)));
     static constexpr int NG = NG0 < NGL ? NG0 : (NGL < 1 ? 1 : NGL);
     static constexpr int NT = NG * GT;
 };
 
 // columns of n_in complex values (zero padded to LY) -> LY spectrum values
-template <typename R, int LY>
+// (HALF: n_in <= LY/2, the first radix pass skips the zero half)
+template <typename R, int LY, bool HALF>
 __global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yfwd(const cpx<R>* __restrict__ in,
                                                                 cpx<R>* __restrict__ out, int n_in,
                                                                 long long ncols,
                                                                 const cpx<R>* __restrict__ twy)
 {
     using S = YPassShape<R, LY>;
-    __shared__ cpx<R> sh[S::NG * LY];
+    __shared__ cpx<R> sh[S::NG * fft_region(LY)];
     const int tid = threadIdx.x, grp = tid / S::GT, g = tid % S::GT;
     const long long c = (long long)blockIdx.x * S::NG + grp;
     if (c >= ncols) return;
     const cpx<R>* src = in + c * n_in;
     cpx<R>* dst = out + c * LY;
-    wave_fft<R, LY, false>(
-        sh + grp * LY, g, twy, 1,
+    wave_fft<R, LY, false, HALF>(
+        sh + grp * fft_region(LY), g, twy, 1,
         [&](int pos) -> cpx<R> { return pos < n_in ? src[pos] : cpx<R>{R(0), R(0)}; },
         [&](int pos, cpx<R> v) { dst[pos] = v; });
 }
 
 // LY spectrum values -> first n_out values of the inverse transform
-template <typename R, int LY>
+// (HALF: n_out <= LY/2, the last radix pass computes only that half)
+template <typename R, int LY, bool HALF>
 __global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yinv(const cpx<R>* __restrict__ in,
                                                                 cpx<R>* __restrict__ out, int n_out,
                                                                 long long ncols,
                                                                 const cpx<R>* __restrict__ twy)
 {
     using S = YPassShape<R, LY>;
-    __shared__ cpx<R> sh[S::NG * LY];
+    __shared__ cpx<R> sh[S::NG * fft_region(LY)];
     const int tid = threadIdx.x, grp = tid / S::GT, g = tid % S::GT;
     const long long c = (long long)blockIdx.x * S::NG + grp;
     if (c >= ncols) return;
     const cpx<R>* src = in + c * LY;
     cpx<R>* dst = out + c * n_out;
-    wave_fft<R, LY, true>(
-        sh + grp * LY, g, twy, 1, [&](int pos) -> cpx<R> { return src[pos]; },
+    wave_fft<R, LY, true, false, HALF>(
+        sh + grp * fft_region(LY), g, twy, 1, [&](int pos) -> cpx<R> { return src[pos]; },
         [&](int pos, cpx<R> v) {
             if (pos < n_out) dst[pos] = v;
         });

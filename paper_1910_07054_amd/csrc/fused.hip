@@ -31,7 +31,7 @@ template <typename R, int LY, int NZMAX, bool ADJ>
 hipError_t fused_a(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
                    int QY, const void* lp, const void* tw, hipStream_t s)
 {
-    const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * LY;
+    const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * fft_region(LY);
     hipError_t e = set_lds((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, bpg, G), dim3(FusedShape<LY>::NT),
@@ -88,7 +88,7 @@ hipError_t fused_ly(int LY, int nz, void* X, int ny, int M, int bpg, int G, cons
 
 bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
 {
-    const size_t lds = (fp64 ? 16 : 8) * 3 * (size_t)nz * LY;
+    const size_t lds = (fp64 ? 16 : 8) * 3 * (size_t)nz * fft_region(LY);
     if (lds_bytes) *lds_bytes = lds;
     if (LY < 8 || LY > 1024) return false;
     if ((fp64 ? nzmax_for<double>(nz, LY) : nzmax_for<float>(nz, LY)) == 0) return false;

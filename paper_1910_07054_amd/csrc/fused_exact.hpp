@@ -11,7 +11,7 @@ template <int LY, int NZ, bool ADJ>
 hipError_t fused_exact_a(void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
                          int QY, const void* lp, const void* tw, hipStream_t s)
 {
-    const size_t lds = sizeof(cpx<float>) * 3 * (size_t)NZ * LY;
+    const size_t lds = sizeof(cpx<float>) * 3 * (size_t)NZ * fft_region(LY);
     constexpr bool own_col0 = LY <= ExactShape<LY>::NT;
     if (lds > 65536) {
         hipError_t e = ensure_lds_limit((const void*)k_ymix_fused_nz<float, LY, NZ, ADJ>, 163840);

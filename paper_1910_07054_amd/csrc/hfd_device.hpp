@@ -4,9 +4,9 @@
 // One FFT of length L is owned by a group of GT = L / V lanes of a single
 // 64-wide wavefront; every lane holds V complex values in registers.  Passes
 // use radix 8 (4 or 2 for the remainder).  Between passes the group exchanges
-// data through its own LDS region of L values (in a bank-spreading order, see
-// lds_swizzle); because the group never spans two wavefronts, no workgroup
-// barrier is needed inside a transform.
+// data through its own LDS region of fft_region(L) slots (L values with one
+// padding slot per eight, see lds_pad); because the group never spans two
+// wavefronts, no workgroup barrier is needed inside a transform.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -127,20 +127,59 @@ __device__ __forceinline__ void dft(cpx<R>* v)
     else dft2<R, INV>(v);
 }
 
-// LDS slot of element `pos` in the intermediate passes of a transform.  The
-// writes of a radix-8 pass go to positions 8j + r (first pass) or
-// 64q + 8r + k (second pass) for the lanes j = 8q + k of a half-wave; stored
-// in natural order those land on 4 or 8 distinct 8-byte bank slots out of 32.
-// Xoring the low five bits of `pos` with a key built from the bits above
-// (bits 5-7 into bits 0-2, bits 6-7 into bits 3-4) spreads both patterns over
-// all 32 slots and leaves the unit-stride reads conflict-free.  The map is a
-// permutation of every aligned block of 32 positions, so a region of L
-// elements (L a power of two) stays a region of L elements.
-__device__ __forceinline__ int lds_swizzle(int pos)
+// Radix-RAD DFT of inputs whose upper half v[RAD/2 ..] is zero (the first
+// pass of a transform of a zero-padded sequence): the butterflies that only
+// add zeros are dropped.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dft_half_in(cpx<R>* v)
 {
-    const int b = pos >> 5;
-    return pos ^ ((b & 7) | (((b >> 1) & 3) << 3));
+    // DFT4 of (a0, a1, 0, 0): (a0 + a1, a0 + rot(a1), a0 - a1, a0 - rot(a1)),
+    // rot = multiplication by -i (forward) or +i (inverse)
+    auto dft4h = [](cpx<R> a0, cpx<R> a1, cpx<R>& b0, cpx<R>& b1, cpx<R>& b2, cpx<R>& b3) {
+        const cpx<R> t = mul_mi<R, INV>(a1);
+        b0 = cadd(a0, a1);
+        b2 = csub(a0, a1);
+        b1 = cadd(a0, t);
+        b3 = csub(a0, t);
+    };
+    if constexpr (RAD == 8) {
+        const R c = R(0.70710678118654752440084436210484903928);
+        cpx<R> e0, e1, e2, e3, o0, o1, o2, o3;
+        dft4h(v[0], v[2], e0, e1, e2, e3);
+        dft4h(v[1], v[3], o0, o1, o2, o3);
+        if (!INV) {
+            o1 = {c * (o1.x + o1.y), c * (o1.y - o1.x)};
+            o3 = {c * (o3.y - o3.x), -c * (o3.x + o3.y)};
+        } else {
+            o1 = {c * (o1.x - o1.y), c * (o1.x + o1.y)};
+            o3 = {-c * (o3.x + o3.y), c * (o3.x - o3.y)};
+        }
+        o2 = mul_mi<R, INV>(o2);
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3);
+        v[7] = csub(e3, o3);
+    } else if constexpr (RAD == 4) {
+        dft4h(v[0], v[1], v[0], v[1], v[2], v[3]);
+    } else {
+        v[1] = v[0];
+    }
 }
+
+// LDS slot of element `pos` in the intermediate passes of a transform: one
+// padding slot after every eight elements, so a transform of length L uses
+// fft_region(L) slots.  The writes of a radix-8 pass go to positions 8j + r
+// (first pass, lane j) and 64q + 8r + k (later passes, lane j = 8q + k); in
+// natural order a half-wave's writes fall on 4 or 8 of the 32 eight-byte bank
+// slots, padded on 32 distinct ones.  A lane's positions differ by multiples
+// of 8 (or by r < 8 from a multiple of 8 in the first pass), so their padded
+// slots differ by compile-time constants and cost no address arithmetic.
+__host__ __device__ constexpr int fft_region(int L) { return L + (L >> 3); }
+__device__ __forceinline__ int lds_pad(int pos) { return pos + (pos >> 3); }
 
 // --- Stockham engine -------------------------------------------------------
 // X[k] = sum_n x[n] exp(-+2 pi i n k / L) (unnormalized in both directions).
@@ -149,7 +188,9 @@ __device__ __forceinline__ int lds_swizzle(int pos)
 // so they are loaded once (Twiddles::load) and reused for every transform the
 // lane runs; inverse transforms use their conjugates.
 // load(pos) supplies x[pos] for the first pass; store(pos, v) receives X[pos]
-// from the last pass; sh is the group's LDS region of L values.
+// from the last pass; sh is the group's LDS region of fft_region(L) slots
+// (the last pass stores through `store`, which may write the region's first
+// L slots in natural order).
 template <int L, int V, int NS>
 struct PassShape {
     static constexpr int REM = L / NS;
@@ -201,7 +242,12 @@ struct Twiddles {
     }
 };
 
-template <typename R, int L, int V, bool INV, int NS, int OFF, bool PRE = false, class Load, class Store>
+// HIN: the input positions L/2 .. L-1 are zero (zero-padded sequence): the
+// first pass neither loads nor transforms them.  HOUT: only the output
+// positions 0 .. L/2-1 are wanted (cropped result): the last pass stores only
+// those, and what feeds nothing else is not computed.
+template <typename R, int L, int V, bool INV, int NS, int OFF, bool PRE = false, bool HIN = false,
+          bool HOUT = false, class Load, class Store>
 __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, const cpx<R>* w,
                                          Load& load, Store& store)
 {
@@ -211,17 +257,26 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
     constexpr int STRIDE = L / RAD;
     constexpr bool FIRST = (NS == 1);
     constexpr bool LAST = P::LAST;
+    constexpr bool HALF_IN = FIRST && HIN;
     static_assert(L % (NS * RAD) == 0, "radix schedule");
+    static_assert(FIRST || STRIDE % 8 == 0, "later passes read at multiples of 8");
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int j = g + GT * u;
+        const int pj = lds_pad(j);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
-            const int pos = j + r * STRIDE;
             if constexpr (FIRST) {
-                if constexpr (!PRE) v[u * RAD + r] = load(pos);
+                // positions j + r STRIDE >= L/2 exactly when r >= RAD/2
+                if constexpr (HALF_IN) {
+                    if (r >= RAD / 2) {
+                        v[u * RAD + r] = {R(0), R(0)};
+                        continue;
+                    }
+                }
+                if constexpr (!PRE) v[u * RAD + r] = load(j + r * STRIDE);
             } else {
-                v[u * RAD + r] = sh[lds_swizzle(pos)];
+                v[u * RAD + r] = sh[pj + r * (STRIDE + STRIDE / 8)];
             }
         }
     }
@@ -235,7 +290,8 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
                 v[u * RAD + r] = cmul(v[u * RAD + r], t);
             }
         }
-        dft<R, RAD, INV>(&v[u * RAD]);
+        if constexpr (HALF_IN) dft_half_in<R, RAD, INV>(&v[u * RAD]);
+        else dft<R, RAD, INV>(&v[u * RAD]);
     }
     if constexpr (!FIRST) wave_sync();
 #pragma unroll
@@ -243,23 +299,29 @@ __device__ __forceinline__ void fft_pass(cpx<R> (&v)[V], cpx<R>* sh, int g, cons
         const int j = g + GT * u;
         const int k = j & (NS - 1);
         const int base = (j - k) * RAD + k;
+        const int pb = lds_pad(base);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
-            const int pos = base + r * NS;
-            if constexpr (LAST) store(pos, v[u * RAD + r]);
-            else sh[lds_swizzle(pos)] = v[u * RAD + r];
+            if constexpr (LAST) {
+                // positions base + r NS >= L/2 exactly when r >= RAD/2
+                if (!HOUT || r < RAD / 2) store(base + r * NS, v[u * RAD + r]);
+            } else {
+                // first pass: (base & 7) + r < 8, so the padded slot is pb + r
+                sh[pb + r * (NS + NS / 8)] = v[u * RAD + r];
+            }
         }
     }
     if constexpr (!LAST) {
         wave_sync();
         constexpr int here = NS > 1 ? NB * (RAD - 1) : 0;
-        fft_pass<R, L, V, INV, P::NEXT, OFF + here>(v, sh, g, w, load, store);
+        fft_pass<R, L, V, INV, P::NEXT, OFF + here, false, false, HOUT>(v, sh, g, w, load, store);
     }
 }
 
 // The values a lane reads in the first pass, in register order, so that the
-// input of several transforms can be requested before any of them starts.
-template <typename R, int L, class Load>
+// input of several transforms can be requested before any of them starts
+// (HIN: the zero upper half is not requested).
+template <typename R, int L, bool HIN = false, class Load>
 __device__ __forceinline__ void fft_first_loads(cpx<R> (&v)[fft_vals(L)], int g, Load load)
 {
     constexpr int V = fft_vals(L), GT = L / V;
@@ -268,39 +330,42 @@ __device__ __forceinline__ void fft_first_loads(cpx<R> (&v)[fft_vals(L)], int g,
 #pragma unroll
     for (int u = 0; u < P::NB; ++u)
 #pragma unroll
-        for (int r = 0; r < P::RAD; ++r) v[u * P::RAD + r] = load(g + GT * u + r * STRIDE);
+        for (int r = 0; r < P::RAD; ++r)
+            v[u * P::RAD + r] = (HIN && r >= P::RAD / 2) ? cpx<R>{R(0), R(0)}
+                                                           : load(g + GT * u + r * STRIDE);
 }
 
 // One transform whose first-pass values are already in v (fft_first_loads).
-template <typename R, int L, bool INV, class Store>
+// sh: the group's LDS region of fft_region(L) values.
+template <typename R, int L, bool INV, bool HIN = false, bool HOUT = false, class Store>
 __device__ __forceinline__ void wave_fft_pre(cpx<R>* sh, int g, const Twiddles<R, L>& tw,
                                              cpx<R> (&v)[fft_vals(L)], Store store)
 {
     constexpr int V = fft_vals(L);
     static_assert(L / V <= 64, "one transform must fit in a wavefront");
     auto none = [](int) { return cpx<R>{R(0), R(0)}; };
-    fft_pass<R, L, V, INV, 1, 0, true>(v, sh, g, tw.w, none, store);
+    fft_pass<R, L, V, INV, 1, 0, true, HIN, HOUT>(v, sh, g, tw.w, none, store);
 }
 
 // One transform with preloaded twiddles.
-template <typename R, int L, bool INV, class Load, class Store>
+template <typename R, int L, bool INV, bool HIN = false, bool HOUT = false, class Load, class Store>
 __device__ __forceinline__ void wave_fft(cpx<R>* sh, int g, const Twiddles<R, L>& tw, Load load,
                                          Store store)
 {
     constexpr int V = fft_vals(L);
     static_assert(L / V <= 64, "one transform must fit in a wavefront");
     cpx<R> v[V];
-    fft_pass<R, L, V, INV, 1, 0>(v, sh, g, tw.w, load, store);
+    fft_pass<R, L, V, INV, 1, 0, false, HIN, HOUT>(v, sh, g, tw.w, load, store);
 }
 
 // One transform loading its own twiddles (single-use callers).
-template <typename R, int L, bool INV, class Load, class Store>
+template <typename R, int L, bool INV, bool HIN = false, bool HOUT = false, class Load, class Store>
 __device__ __forceinline__ void wave_fft(cpx<R>* sh, int g, const cpx<R>* __restrict__ tw, int tws,
                                          Load load, Store store)
 {
     Twiddles<R, L> t;
     t.load(g, tw, tws);
-    wave_fft<R, L, INV>(sh, g, t, load, store);
+    wave_fft<R, L, INV, HIN, HOUT>(sh, g, t, load, store);
 }
 
 }  // namespace hfd

@@ -23,7 +23,7 @@ hipError_t ensure_lds_limit(const void* kernel, int bytes);
 
 // x pass, forward / inverse (R = float if !fp64 else double) over nsig * ny
 // rows; ty = rows per block (0: the default tile; else one of 4, 8, 16, 24,
-// 32 where x_tile_supported)
+// 32 where x_tile_supported, for rows of nx <= LX/2 values only)
 bool x_tile_supported(bool fp64, int LX, int ty);
 hipError_t launch_xfwd(bool fp64, int LX, const void* in, void* out, int nx, int ny,
                        long long in_sig_stride, int in_row_stride, int nsig, const void* twx,

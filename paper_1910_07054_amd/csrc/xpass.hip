@@ -1,5 +1,9 @@
 // Instances of the x-pass kernels for every padded length 8..4096, with the
-// rows per block (TY) chosen at run time among the compiled tile sizes.
+// rows per block (TY) chosen at run time among the compiled tile sizes.  The
+// field path (rows of nx <= LX/2 values) runs the HALF kernels, which skip
+// the zero half in the first radix pass (forward) or the cropped half in the
+// last (inverse); full rows (the tensor transforms) run the default tile
+// without that pruning.
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
@@ -16,33 +20,33 @@ constexpr bool x_tile_ok()
     return S::GT * TY <= 1024 && S::GT * TY >= 64 && S::LDS <= 163840;
 }
 
-template <typename R, int LX, int TY>
+template <typename R, int LX, int TY, bool HALF>
 hipError_t xfwd_t(const void* in, void* out, int nx, int ny, long long iss, int irs, int nsig,
                   const void* tw, hipStream_t s)
 {
     using S = XPassShape<R, LX, TY>;
-    hipError_t e = ensure_lds_limit((const void*)k_xfwd<R, LX, TY>, (int)S::LDS);
+    hipError_t e = ensure_lds_limit((const void*)k_xfwd<R, LX, TY, HALF>, (int)S::LDS);
     if (e != hipSuccess) return e;
     const long long rows = (long long)nsig * ny;
     if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)((rows + S::TY - 1) / S::TY));
-    hipLaunchKernelGGL((k_xfwd<R, LX, TY>), grid, dim3(S::NT), S::LDS, s, (const R*)in, (cpx<R>*)out,
-                       nx, ny, (int)rows, iss, irs, (const cpx<R>*)tw);
+    hipLaunchKernelGGL((k_xfwd<R, LX, TY, HALF>), grid, dim3(S::NT), S::LDS, s, (const R*)in,
+                       (cpx<R>*)out, nx, ny, (int)rows, iss, irs, (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
-template <typename R, int LX, int TY>
+template <typename R, int LX, int TY, bool HALF>
 hipError_t xinv_t(const void* in, void* out, int nx, int ny, long long oss, int ors, int nsig,
                   const void* tw, hipStream_t s)
 {
     using S = XPassShape<R, LX, TY>;
-    hipError_t e = ensure_lds_limit((const void*)k_xinv<R, LX, TY>, (int)S::LDS);
+    hipError_t e = ensure_lds_limit((const void*)k_xinv<R, LX, TY, HALF>, (int)S::LDS);
     if (e != hipSuccess) return e;
     const long long rows = (long long)nsig * ny;
     if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)((rows + S::TY - 1) / S::TY));
-    hipLaunchKernelGGL((k_xinv<R, LX, TY>), grid, dim3(S::NT), S::LDS, s, (const cpx<R>*)in, (R*)out,
-                       nx, ny, (int)rows, oss, ors, (const cpx<R>*)tw);
+    hipLaunchKernelGGL((k_xinv<R, LX, TY, HALF>), grid, dim3(S::NT), S::LDS, s, (const cpx<R>*)in,
+                       (R*)out, nx, ny, (int)rows, oss, ors, (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
@@ -50,12 +54,18 @@ template <bool FWD, typename R, int LX, int TY>
 hipError_t x_one(const void* in, void* out, int nx, int ny, long long ss, int rs, int nsig,
                  const void* tw, hipStream_t s)
 {
+    const bool half = 2 * nx <= LX;
     if constexpr (TY == 0 || x_tile_ok<R, LX, TY>()) {
-        if constexpr (FWD) return xfwd_t<R, LX, TY>(in, out, nx, ny, ss, rs, nsig, tw, s);
-        else return xinv_t<R, LX, TY>(in, out, nx, ny, ss, rs, nsig, tw, s);
-    } else {
-        return hipErrorInvalidValue;
+        if (half) {
+            if constexpr (FWD) return xfwd_t<R, LX, TY, true>(in, out, nx, ny, ss, rs, nsig, tw, s);
+            else return xinv_t<R, LX, TY, true>(in, out, nx, ny, ss, rs, nsig, tw, s);
+        }
+        if constexpr (TY == 0) {
+            if constexpr (FWD) return xfwd_t<R, LX, 0, false>(in, out, nx, ny, ss, rs, nsig, tw, s);
+            else return xinv_t<R, LX, 0, false>(in, out, nx, ny, ss, rs, nsig, tw, s);
+        }
     }
+    return hipErrorInvalidValue;
 }
 
 template <bool FWD, typename R, int LX>
@@ -100,7 +110,7 @@ bool x_tile_supported(bool fp64, int LX, int ty)
     if (ty != 4 && ty != 8 && ty != 16 && ty != 24 && ty != 32) return false;
     const int M = LX / 2;
     const int V = fft_vals(M), GT = M / V;
-    const size_t lds = (fp64 ? 16 : 8) * (size_t)ty * (M + 1);
+    const size_t lds = (fp64 ? 16 : 8) * (size_t)ty * (size_t)(fft_region(M) | 1);
     return GT * ty <= 1024 && GT * ty >= 64 && lds <= 163840;
 }
 

@@ -4,6 +4,8 @@
 
 namespace hfd {
 
+// half: the column holds at most LY/2 values (the field path; the tensor
+// transforms run on full columns)
 template <typename R, int LY>
 static hipError_t yfwd_t(const void* in, void* out, int n, long long ncols, const void* tw,
                          hipStream_t s)
@@ -11,8 +13,12 @@ static hipError_t yfwd_t(const void* in, void* out, int n, long long ncols, cons
     using S = YPassShape<R, LY>;
     const long long nb = (ncols + S::NG - 1) / S::NG;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_yfwd<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<R>*)in,
-                       (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    if (2 * n <= LY)
+        hipLaunchKernelGGL((k_yfwd<R, LY, true>), dim3((unsigned)nb), dim3(S::NT), 0, s,
+                           (const cpx<R>*)in, (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    else
+        hipLaunchKernelGGL((k_yfwd<R, LY, false>), dim3((unsigned)nb), dim3(S::NT), 0, s,
+                           (const cpx<R>*)in, (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
@@ -23,8 +29,12 @@ static hipError_t yinv_t(const void* in, void* out, int n, long long ncols, cons
     using S = YPassShape<R, LY>;
     const long long nb = (ncols + S::NG - 1) / S::NG;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_yinv<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<R>*)in,
-                       (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    if (2 * n <= LY)
+        hipLaunchKernelGGL((k_yinv<R, LY, true>), dim3((unsigned)nb), dim3(S::NT), 0, s,
+                           (const cpx<R>*)in, (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
+    else
+        hipLaunchKernelGGL((k_yinv<R, LY, false>), dim3((unsigned)nb), dim3(S::NT), 0, s,
+                           (const cpx<R>*)in, (cpx<R>*)out, n, ncols, (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
