@@ -390,6 +390,13 @@ hfd_status alloc_setup_scratch(hfd_plan p)
 // plan's setup scratch; after each chunk pack(first, count, F) enqueues the
 // packing of spectra F[count][6][M][Ly] (complex, interleaved re/im doubles).
 // Synchronizes the stream at the end.
+static double max_thickness(const std::vector<PairGeoH>& geos, int first, int count)
+{
+    double t = 0.0;
+    for (int u = first; u < first + count; ++u) t = std::max(t, std::max(geos[u].ti, geos[u].tj));
+    return t;
+}
+
 template <class Pack>
 hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
 {
@@ -406,7 +413,8 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
         const int np = std::min(CP, n - u0);
         e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
         if (e == hipSuccess)
-            e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 0, s);
+            e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy,
+                                   max_thickness(geos, u0, np), 0, s);
         if (e == hipSuccess)
             e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
         if (e == hipSuccess)
@@ -1414,7 +1422,9 @@ hfd_status hfd_export_real_tensor(hfd_plan p, int geom, int i, int j, double* ds
     PairGeoH h = {t[i], t[j], z[i] - z[j], 0.0};
     hipError_t e = hipMemcpyAsync(pg, &h, sizeof(h), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(W, 0, n * 8, s);
-    if (e == hipSuccess) e = launch_tensor_real(W, pg, 1, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy, 1, s);
+    if (e == hipSuccess)
+        e = launch_tensor_real(W, pg, 1, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy,
+                               std::max(h.ti, h.tj), 1, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dst, W, n * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(W);

@@ -130,8 +130,9 @@ hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz,
 struct PairGeoH {
     double ti, tj, Z, pad;
 };
+// tmax: the largest thickness among the npairs pair records (bounds the near box)
 hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
-                              int Ly, double dx, double dy, int mode, hipStream_t s);
+                              int Ly, double dx, double dy, double tmax, int mode, hipStream_t s);
 // zero n doubles (a kernel, so that graph captures hold no memset node)
 hipError_t launch_zero64(double* p, long long n, hipStream_t s);
 // zero what k_dtensor_real leaves untouched in nplanes padded Lx x Ly planes

@@ -1,6 +1,7 @@
 // Instances of the FP64 tensor-setup kernels.
 #include "launch.hpp"
 #include <algorithm>
+#include <cmath>
 #include "tensor_kernels.hpp"
 
 namespace hfd {
@@ -8,13 +9,28 @@ namespace hfd {
 static_assert(sizeof(PairGeo) == sizeof(PairGeoH), "pair record layout");
 
 hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
-                              int Ly, double dx, double dy, int mode, hipStream_t s)
+                              int Ly, double dx, double dy, double tmax, int mode, hipStream_t s)
 {
-    const long long n = (long long)nx * ny * npairs;
-    const long long nb = (n + 127) / 128;
-    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tensor_real, dim3((unsigned)nb), dim3(128), 0, s, W, (const PairGeo*)pg,
-                       npairs, nx, ny, Lx, Ly, dx, dy, mode);
+    if (npairs <= 0 || nx <= 0 || ny <= 0) return hipSuccess;
+    // boxes of every entry with rho < 6 and rho < 32: p dx and q dy stay below
+    // rho max(dx, dy, t)
+    const double dmax = std::max(std::max(dx, dy), tmax);
+    const int pn = (int)std::min<double>(nx, std::floor(kNearRho * dmax / dx) + 2.0);
+    const int qn = (int)std::min<double>(ny, std::floor(kNearRho * dmax / dy) + 2.0);
+    const int pm = (int)std::min<double>(nx, std::floor(kMidRho * dmax / dx) + 2.0);
+    const int qm = (int)std::min<double>(ny, std::floor(kMidRho * dmax / dy) + 2.0);
+    const long long tiles = (long long)((nx + 15) / 16) * ((ny + 15) / 16);
+    const int epb = 256 / kMidLanes;
+    if (tiles * npairs > 0x7fffffffLL || npairs > 65535) return hipErrorInvalidValue;
+    const dim3 ngrid((unsigned)((pn + kNTile - 1) / kNTile), (unsigned)((qn + kNTile - 1) / kNTile),
+                     (unsigned)npairs);
+    hipLaunchKernelGGL(k_tensor_near, ngrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, Lx, Ly,
+                       dx, dy, mode, pn, qn);
+    const dim3 mgrid((unsigned)((pm * qm + epb - 1) / epb), (unsigned)npairs);
+    hipLaunchKernelGGL(k_tensor_mid, mgrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, Lx, Ly,
+                       dx, dy, mode, pm, qm);
+    hipLaunchKernelGGL(k_tensor_far, dim3((unsigned)(tiles * npairs)), dim3(256), 0, s, W,
+                       (const PairGeo*)pg, npairs, nx, ny, Lx, Ly, dx, dy, mode);
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@
 //   N_kl = -1/(4 pi |tau|) int_tau int_tau' (3 r_k r_l - r^2 delta_kl) / r^5,
 // written as a one-dimensional integral per axis over the difference
 // coordinate with the overlap (triangle / trapezoid) weight, split at its
-// kinks; n = 5, 4, 3 points per piece for rho < 12, < 32, beyond.
+// kinks; n = 5, 4, 3, 2 points per piece for rho < 12, < 32, < 100, beyond
+// (the 2-point rule's error there is ~1e-9 of the entry and falls as rho^-4).
 #pragma once
 #include "hfd_device.hpp"
 
@@ -158,123 +159,174 @@ __device__ inline double dphi_dz_c(int c, double x, double y, double z)
     }
 }
 
-__device__ inline void newell_entry(double X, double Y, double Z, double dx, double dy, double ti,
-                                    double tj, double* out)
+// Gauss-Legendre rules on [-1, 1] with n = 2 .. 5 points (row n - 2).
+struct GLTable {
+    double x[4][5], w[4][5];
+};
+constexpr GLTable kGL = {
+    {{-0.57735026918962576451, 0.57735026918962576451},
+     {-0.77459666924148337704, 0.0, 0.77459666924148337704},
+     {-0.86113631159405257522, -0.3399810435848562648, 0.3399810435848562648, 0.86113631159405257522},
+     {-0.9061798459386639928, -0.53846931010568309104, 0.0, 0.53846931010568309104,
+      0.9061798459386639928}},
+    {{1.0, 1.0},
+     {0.55555555555555555556, 0.88888888888888888889, 0.55555555555555555556},
+     {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263, 0.34785484513745385737},
+     {0.23692688505618908751, 0.47862867049936646804, 0.56888888888888888889, 0.47862867049936646804,
+      0.23692688505618908751}}};
+// the same table in device memory, for loops over nodes that are not unrolled
+__constant__ GLTable kGLDev = kGL;
+
+// 1 / sqrt(r2) from the hardware estimate and one Newton step for
+// f(y) = y^-2 - r2 (the estimate's relative error e becomes ~1.5 e^2)
+__device__ inline double rsqrt_newton(double r2)
 {
-    const double ox[3] = {dx, 0.0, -dx}, oy[3] = {dy, 0.0, -dy}, w3[3] = {1.0, -2.0, 1.0};
-    const double oz[4] = {ti, 0.0, ti - tj, -tj}, w4[4] = {1.0, -1.0, -1.0, 1.0};
-    const double pref = -1.0 / (4.0 * M_PI * dx * dy * ti);
-    for (int c = 0; c < 6; ++c) {
-        double acc = 0.0;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                double s = 0.0;
-                for (int k = 0; k < 4; ++k) s += w4[k] * phi_c(c, X + ox[a], Y + oy[b], Z + oz[k]);
-                acc += w3[a] * w3[b] * s;
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Cell average of the dipole kernel by n-point Gauss-Legendre quadrature.
+// Lateral axes: the difference coordinate u in [-d, d] with weight d - |u|,
+// written as the points X + u_k and X - u_k for the nodes u_k of [0, d] (the
+// kink at u = 0 is an end point).  For one z point and one y point the x sums
+//   A0 = sum w r^-5,  A1 = sum w x r^-5,  A2 = sum w x^2 r^-5
+// give every component: with c = y^2 + z^2,
+//   xx: 2 A2 - c A0,   yy: (2 y^2 - z^2) A0 - A2,   xy: 3 y A1,
+//   xz: 3 z A1,        yz: 3 y z A0,                zz = -(xx + yy);
+// the y sums of A0, y A0, y^2 A0, A1, y A1, A2 carry them to the z level.
+// gl_znode adds the weighted contribution of one z point to S = (xx, yy, xy,
+// xz, yz).
+template <int N>
+__device__ inline void gl_znode(const double* xp, const double* xm, const double* wx, double Y,
+                                double dy, double z, double wz, double* S)
+{
+    constexpr int R = N - 2;
+    const double z2 = z * z;
+    double B0 = 0.0, By = 0.0, Byy = 0.0, B1 = 0.0, B1y = 0.0, B2 = 0.0;
+#pragma unroll
+    for (int ky = 0; ky < N; ++ky) {
+        const double uy = 0.5 * dy * (1.0 + kGL.x[R][ky]);
+        const double wy = 0.5 * dy * kGL.w[R][ky] * (dy - uy);
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const double y = sy ? Y - uy : Y + uy;
+            const double c = fma(y, y, z2);
+            double A0 = 0.0, A1 = 0.0, A2 = 0.0;
+#pragma unroll
+            for (int kx = 0; kx < N; ++kx) {
+#pragma unroll
+                for (int sx = 0; sx < 2; ++sx) {
+                    const double x = sx ? xm[kx] : xp[kx];
+                    const double ir = rsqrt_newton(fma(x, x, c));
+                    const double ir2 = ir * ir;
+                    const double w5 = wx[kx] * (ir2 * ir2 * ir);
+                    const double t = w5 * x;
+                    A0 += w5;
+                    A1 += t;
+                    A2 = fma(t, x, A2);
+                }
             }
-        out[c] = pref * acc;
+            const double t0 = wy * A0, t1 = wy * A1, ty0 = t0 * y;
+            B0 += t0;
+            By += ty0;
+            Byy = fma(ty0, y, Byy);
+            B1 += t1;
+            B1y = fma(t1, y, B1y);
+            B2 = fma(wy, A2, B2);
+        }
+    }
+    S[0] = fma(wz, 2.0 * B2 - Byy - z2 * B0, S[0]);
+    S[1] = fma(wz, 2.0 * Byy - z2 * B0 - B2, S[1]);
+    S[2] = fma(wz, 3.0 * B1y, S[2]);
+    S[3] = fma(wz, 3.0 * z * B1, S[3]);
+    S[4] = fma(wz, 3.0 * z * By, S[4]);
+}
+
+// z axis: for n >= 3 the difference coordinate v = s - s' in [-tj, ti] with
+// weight |[0, ti] cap [v, v + tj]|, linear on the pieces split at 0 and
+// ti - tj (3n points, 2n for equal thicknesses); for n = 2 the product of the
+// two cells' own 2-point rules (4 points; the same error order, fewer points
+// when the thicknesses differ).  z_node gives point k of the list (k < 4 for
+// n = 2, k < 3n otherwise) and its weight; false for the points of an empty
+// piece.
+template <int N>
+__device__ inline bool z_node(int k, double ti, double tj, double& v, double& wz)
+{
+    constexpr int R = N - 2;
+    if (N == 2) {
+        v = 0.5 * ti * (1.0 + kGLDev.x[0][k >> 1]) - 0.5 * tj * (1.0 + kGLDev.x[0][k & 1]);
+        wz = 0.25 * ti * tj;
+        return true;
+    }
+    const int piece = k / N, kz = k - piece * N;
+    const double a = fmin(0.0, ti - tj), b = fmax(0.0, ti - tj);
+    const double lo = piece == 0 ? -tj : (piece == 1 ? a : b);
+    const double hi = piece == 0 ? a : (piece == 1 ? b : ti);
+    const double L = hi - lo;
+    if (!(L > 0.0)) return false;
+    v = lo + 0.5 * L * (1.0 + kGLDev.x[R][kz]);
+    wz = 0.5 * L * kGLDev.w[R][kz] * (fmin(ti, v + tj) - fmax(0.0, v));
+    return true;
+}
+template <int N>
+__device__ inline int z_count()
+{
+    return N == 2 ? 4 : 3 * N;
+}
+
+// lateral nodes of the x axis: X + u_k, X - u_k and their weight
+template <int N>
+__device__ inline void x_nodes(double X, double dx, double* xp, double* xm, double* wx)
+{
+    constexpr int R = N - 2;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double u = 0.5 * dx * (1.0 + kGL.x[R][k]);
+        xp[k] = X + u;
+        xm[k] = X - u;
+        wx[k] = 0.5 * dx * kGL.w[R][k] * (dx - u);
     }
 }
 
-template <int N>
-struct GLRule;
-template <>
-struct GLRule<3> {
-    static constexpr double x[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
-    static constexpr double w[3] = {0.55555555555555555556, 0.88888888888888888889,
-                                    0.55555555555555555556};
-};
-template <>
-struct GLRule<4> {
-    static constexpr double x[4] = {-0.86113631159405257522, -0.3399810435848562648,
-                                    0.3399810435848562648, 0.86113631159405257522};
-    static constexpr double w[4] = {0.34785484513745385737, 0.65214515486254614263,
-                                    0.65214515486254614263, 0.34785484513745385737};
-};
-template <>
-struct GLRule<5> {
-    static constexpr double x[5] = {-0.9061798459386639928, -0.53846931010568309104, 0.0,
-                                    0.53846931010568309104, 0.9061798459386639928};
-    static constexpr double w[5] = {0.23692688505618908751, 0.47862867049936646804,
-                                    0.56888888888888888889, 0.47862867049936646804,
-                                    0.23692688505618908751};
-};
+// the six components from the z-level sums S = (xx, yy, xy, xz, yz)
+__device__ inline void gl_finish(const double* S, double dx, double dy, double ti, double* out)
+{
+    const double pref = -1.0 / (4.0 * M_PI * dx * dy * ti);
+    out[0] = pref * S[0];
+    out[1] = pref * S[1];
+    out[2] = -(out[0] + out[1]);
+    out[3] = pref * S[2];
+    out[4] = pref * S[3];
+    out[5] = pref * S[4];
+}
 
 template <int N>
 __device__ inline void gl_entry(double X, double Y, double Z, double dx, double dy, double ti,
                                 double tj, double* out)
 {
-    using G = GLRule<N>;
-    // lateral difference coordinate u in [-d, d], weight (d - |u|)
-    double xs[2 * N], wx[2 * N], ys[2 * N], wy[2 * N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const double ux = 0.5 * dx * (1.0 + G::x[k]), wxk = 0.5 * dx * G::w[k] * (dx - ux);
-        xs[k] = X + ux; xs[N + k] = X - ux; wx[k] = wxk; wx[N + k] = wxk;
-        const double uy = 0.5 * dy * (1.0 + G::x[k]), wyk = 0.5 * dy * G::w[k] * (dy - uy);
-        ys[k] = Y + uy; ys[N + k] = Y - uy; wy[k] = wyk; wy[N + k] = wyk;
+    double xp[N], xm[N], wx[N];
+    x_nodes<N>(X, dx, xp, xm, wx);
+    double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < z_count<N>(); ++k) {
+        double v, wz;
+        if (z_node<N>(k, ti, tj, v, wz)) gl_znode<N>(xp, xm, wx, Y, dy, Z + v, wz, S);
     }
-    // z difference v = s - s' in [-tj, ti], weight |[0, ti] cap [v, v + tj]|,
-    // linear on the pieces split at 0 and ti - tj
-    double zs[3 * N], wz[3 * N];
-    int nzn = 0;
-    const double a = fmin(0.0, ti - tj), b = fmax(0.0, ti - tj);
-    const double lo[3] = {-tj, a, b}, hi[3] = {a, b, ti};
-#pragma unroll
-    for (int piece = 0; piece < 3; ++piece) {
-        const double L = hi[piece] - lo[piece];
-        if (!(L > 0.0)) continue;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const double v = lo[piece] + 0.5 * L * (1.0 + G::x[k]);
-            zs[nzn] = Z + v;
-            wz[nzn] = 0.5 * L * G::w[k] * (fmin(ti, v + tj) - fmax(0.0, v));
-            ++nzn;
-        }
-    }
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int iz = 0; iz < nzn; ++iz) {
-        const double z = zs[iz];
-        double az[6] = {0, 0, 0, 0, 0, 0};
-        for (int iy = 0; iy < 2 * N; ++iy) {
-            const double y = ys[iy];
-            double ay[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int ix = 0; ix < 2 * N; ++ix) {
-                const double x = xs[ix];
-                const double r2 = x * x + y * y + z * z;
-                const double ir = 1.0 / sqrt(r2);
-                const double ir2 = ir * ir;
-                const double w5 = wx[ix] * ir2 * ir2 * ir;
-                ay[0] += w5 * (3.0 * x * x - r2);
-                ay[1] += w5 * (3.0 * y * y - r2);
-                ay[2] += w5 * (3.0 * z * z - r2);
-                ay[3] += w5 * (3.0 * x * y);
-                ay[4] += w5 * (3.0 * x * z);
-                ay[5] += w5 * (3.0 * y * z);
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) az[c] += wy[iy] * ay[c];
-        }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += wz[iz] * az[c];
-    }
-    const double pref = -1.0 / (4.0 * M_PI * dx * dy * ti);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) out[c] = pref * acc[c];
+    gl_finish(S, dx, dy, ti, out);
 }
 
-__device__ inline void tensor_entry(double X, double Y, double Z, double dx, double dy, double ti,
-                                    double tj, double* out)
+// Centre distance of the entry in units of the largest cell size; decides
+// between the 64-term form (rho < 6) and quadrature.  No contraction, so that
+// the two kernels below, which split the entries by it, round it alike.
+__device__ inline double entry_rho(double X, double Y, double Z, double dx, double dy, double ti,
+                                   double tj)
 {
+#pragma clang fp contract(off)
     const double zc = Z + 0.5 * (ti - tj);
     const double dmax = fmax(fmax(dx, dy), fmax(ti, tj));
-    const double rho = sqrt(X * X + Y * Y + zc * zc) / dmax;
-    if (rho < 6.0) newell_entry(X, Y, Z, dx, dy, ti, tj, out);
-    else if (rho < 12.0) gl_entry<5>(X, Y, Z, dx, dy, ti, tj, out);
-    else if (rho < 32.0) gl_entry<4>(X, Y, Z, dx, dy, ti, tj, out);
-    else gl_entry<3>(X, Y, Z, dx, dy, ti, tj, out);
+    return sqrt(X * X + Y * Y + zc * zc) / dmax;
 }
+constexpr double kNearRho = 6.0, kMidRho = 32.0;
 
 // parity sign of component c under x -> -x (sx = -1) and y -> -y (sy = -1)
 __device__ inline double parity_sign(int c, int sx, int sy)
@@ -287,52 +339,156 @@ __device__ inline double parity_sign(int c, int sx, int sy)
     }
 }
 
-// Real-space tensor of `npairs` pairs on the quadrant p in [0, nx), q in [0, ny).
-// mode 0: write the zero-padded periodic arrays W[pair][6][Ly][Lx] (all four
-//         sign images); W must be zeroed beforehand.
-// mode 1: write the offset table W[pair][6][2ny-1][2nx-1].
-__global__ __launch_bounds__(128) void k_tensor_real(double* __restrict__ W,
-                                                     const PairGeo* __restrict__ pg, int npairs,
-                                                     int nx, int ny, int Lx, int Ly, double dx,
-                                                     double dy, int mode)
+// Write component c of the quadrant entry (p, q) of pair u with its sign images.
+// mode 0: the zero-padded periodic arrays W[pair][6][Ly][Lx] (W zeroed beforehand);
+// mode 1: the offset table W[pair][6][2ny-1][2nx-1].
+__device__ inline void store_component(double* __restrict__ W, int mode, int u, int c, int p, int q,
+                                       double v, int nx, int ny, int Lx, int Ly)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)nx * ny;
-    if (idx >= per * npairs) return;
-    const int u = (int)(idx / per);
-    const int q = (int)((idx / nx) % ny), p = (int)(idx % nx);
-    const PairGeo G = pg[u];
-    double N[6];
-    tensor_entry(p * dx, q * dy, G.Z, dx, dy, G.ti, G.tj, N);
-    if (p == 0) { N[3] = 0.0; N[4] = 0.0; }  // odd in x
-    if (q == 0) { N[3] = 0.0; N[5] = 0.0; }  // odd in y
+    if ((p == 0 && (c == 3 || c == 4)) || (q == 0 && (c == 3 || c == 5))) v = 0.0;  // odd axes
     if (mode == 0) {
         const long long plane = (long long)Lx * Ly;
-        double* base = W + (long long)u * 6 * plane;
+        double* base = W + ((long long)u * 6 + c) * plane;
         for (int sy = 1; sy >= -1; sy -= 2) {
             if (sy < 0 && q == 0) continue;
             const int qq = sy > 0 ? q : Ly - q;
             for (int sx = 1; sx >= -1; sx -= 2) {
                 if (sx < 0 && p == 0) continue;
                 const int pp = sx > 0 ? p : Lx - p;
-                for (int c = 0; c < 6; ++c)
-                    base[c * plane + (long long)qq * Lx + pp] = parity_sign(c, sx, sy) * N[c];
+                base[(long long)qq * Lx + pp] = parity_sign(c, sx, sy) * v;
             }
         }
     } else {
         const int Wo = 2 * nx - 1, Ho = 2 * ny - 1;
-        const long long plane = (long long)Wo * Ho;
-        double* base = W + (long long)u * 6 * plane;
+        double* base = W + ((long long)u * 6 + c) * Wo * Ho;
         for (int sy = 1; sy >= -1; sy -= 2) {
             if (sy < 0 && q == 0) continue;
             for (int sx = 1; sx >= -1; sx -= 2) {
                 if (sx < 0 && p == 0) continue;
-                const int pi = sx * p + nx - 1, qi = sy * q + ny - 1;
-                for (int c = 0; c < 6; ++c)
-                    base[c * plane + (long long)qi * Wo + pi] = parity_sign(c, sx, sy) * N[c];
+                base[(long long)(sy * q + ny - 1) * Wo + (sx * p + nx - 1)] = parity_sign(c, sx, sy) * v;
             }
         }
     }
+}
+
+// Real-space tensor of `npairs` pairs on the quadrant p in [0, nx), q in [0, ny),
+// in three launches that split the entries at rho = 6 and rho = 32 (see
+// store_component for the output modes).
+//
+// Near entries (64-term form) on tiles of kNTile x kNTile entries of the box
+// p < pn, q < qn that holds every entry with rho < 6.  The lateral stencil
+// points of neighbouring entries are the lattice points themselves, so a
+// block first evaluates Phi_c at the tile's lattice points plus a one-point
+// halo, for the four z offsets of the z stencil (LDS), then each (entry,
+// component) applies the 3 x 3 x 4 stencil from there: 2.25 evaluations per
+// entry and term instead of 9, in the summation order of the direct sum.
+// Items are ordered component-major so that a wave evaluates one Phi_c.
+constexpr int kNTile = 4;
+__global__ __launch_bounds__(256) void k_tensor_near(double* __restrict__ W,
+                                                     const PairGeo* __restrict__ pg, int nx, int ny,
+                                                     int Lx, int Ly, double dx, double dy, int mode,
+                                                     int pn, int qn)
+{
+    constexpr int E = kNTile + 2, EE = E * E;
+    __shared__ double F[6][4][EE];
+    const int u = blockIdx.z;
+    const int p0 = blockIdx.x * kNTile, q0 = blockIdx.y * kNTile;
+    const PairGeo G = pg[u];
+    const double oz[4] = {G.ti, 0.0, G.ti - G.tj, -G.tj};
+    for (int i = threadIdx.x; i < 6 * 4 * EE; i += blockDim.x) {
+        const int c = i / (4 * EE), k = (i / EE) % 4, e = i % EE;
+        const int ey = e / E, ex = e - ey * E;
+        F[c][k][e] = phi_c(c, (double)(p0 + ex - 1) * dx, (double)(q0 + ey - 1) * dy, G.Z + oz[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x >= 6 * kNTile * kNTile) return;
+    const int c = threadIdx.x / (kNTile * kNTile), t = threadIdx.x % (kNTile * kNTile);
+    const int tx = t % kNTile, ty = t / kNTile;
+    const int p = p0 + tx, q = q0 + ty;
+    if (p >= pn || q >= qn || p >= nx || q >= ny) return;
+    if (!(entry_rho(p * dx, q * dy, G.Z, dx, dy, G.ti, G.tj) < kNearRho)) return;
+    // offsets {+d, 0, -d} with weights {1, -2, 1}; z weights {1, -1, -1, 1}
+    const int oi[3] = {1, 0, -1};
+    const double w3[3] = {1.0, -2.0, 1.0}, w4[4] = {1.0, -1.0, -1.0, 1.0};
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const int e = (ty + 1 + oi[b]) * E + (tx + 1 + oi[a]);
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += w4[k] * F[c][k][e];
+            acc += w3[a] * w3[b] * s;
+        }
+    const double pref = -1.0 / (4.0 * M_PI * dx * dy * G.ti);
+    store_component(W, mode, u, c, p, q, pref * acc, nx, ny, Lx, Ly);
+}
+
+// Entries with 6 <= rho < 32 (5 and 4 points per piece, up to 15 z points
+// of 100 and 64 lateral points each) over the box p < pm, q < qm that holds
+// them: 16 lanes per entry, one z point per lane, summed across the lanes, so
+// that no lane runs the whole entry alone.
+constexpr int kMidLanes = 16;
+__global__ __launch_bounds__(256) void k_tensor_mid(double* __restrict__ W,
+                                                    const PairGeo* __restrict__ pg, int nx, int ny,
+                                                    int Lx, int Ly, double dx, double dy, int mode,
+                                                    int pm, int qm)
+{
+    const int l = threadIdx.x % kMidLanes;
+    const int e = blockIdx.x * (256 / kMidLanes) + threadIdx.x / kMidLanes;
+    const int u = blockIdx.y;
+    // every test below is the same for the 16 lanes of an entry
+    if (e >= pm * qm) return;
+    const int p = e % pm, q = e / pm;
+    if (p >= nx || q >= ny) return;
+    const PairGeo G = pg[u];
+    const double X = p * dx, Y = q * dy;
+    const double rho = entry_rho(X, Y, G.Z, dx, dy, G.ti, G.tj);
+    if (rho < kNearRho || !(rho < kMidRho)) return;
+    double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double v, wz;
+    if (rho < 12.0) {
+        double xp[5], xm[5], wx[5];
+        x_nodes<5>(X, dx, xp, xm, wx);
+        if (l < z_count<5>() && z_node<5>(l, G.ti, G.tj, v, wz))
+            gl_znode<5>(xp, xm, wx, Y, dy, G.Z + v, wz, S);
+    } else {
+        double xp[4], xm[4], wx[4];
+        x_nodes<4>(X, dx, xp, xm, wx);
+        if (l < z_count<4>() && z_node<4>(l, G.ti, G.tj, v, wz))
+            gl_znode<4>(xp, xm, wx, Y, dy, G.Z + v, wz, S);
+    }
+#pragma unroll
+    for (int off = kMidLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) S[i] += __shfl_xor(S[i], off, kMidLanes);
+    double N[6];
+    gl_finish(S, dx, dy, G.ti, N);
+    if (l < 6) store_component(W, mode, u, l, p, q, N[l], nx, ny, Lx, Ly);
+}
+
+// Entries with rho >= 32 (3 points per piece below rho = 100, 2 beyond), one
+// thread per entry: blocks of 16 x 16 entries, 8 x 8 per wave.  The block
+// index runs over the pairs fastest and then over the tile rows from the
+// origin outwards, so that the tiles with the most points start first.
+__global__ __launch_bounds__(256) void k_tensor_far(double* __restrict__ W,
+                                                    const PairGeo* __restrict__ pg, int npairs,
+                                                    int nx, int ny, int Lx, int Ly, double dx,
+                                                    double dy, int mode)
+{
+    const int u = (int)(blockIdx.x % (unsigned)npairs), t = (int)(blockIdx.x / (unsigned)npairs);
+    const int ntx = (nx + 15) / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = (t % ntx) * 16 + (w & 1) * 8 + (lane & 7);
+    const int q = (t / ntx) * 16 + (w >> 1) * 8 + (lane >> 3);
+    if (p >= nx || q >= ny) return;
+    const PairGeo G = pg[u];
+    const double X = p * dx, Y = q * dy;
+    const double rho = entry_rho(X, Y, G.Z, dx, dy, G.ti, G.tj);
+    if (rho < kMidRho) return;
+    double N[6];
+    if (rho < 100.0) gl_entry<3>(X, Y, G.Z, dx, dy, G.ti, G.tj, N);
+    else gl_entry<2>(X, Y, G.Z, dx, dy, G.ti, G.tj, N);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) store_component(W, mode, u, c, p, q, N[c], nx, ny, Lx, Ly);
 }
 
 // Lateral-stencilled z-derivative of Phi at height zeta (one per distinct
@@ -362,7 +518,7 @@ __global__ __launch_bounds__(kDTile * kDTile) void k_dtensor_real(double* __rest
     const int tx = threadIdx.x % kDTile, ty = threadIdx.x / kDTile;
     const int p = p0 + tx, q = q0 + ty;
     if (p >= nx || q >= ny) return;
-    // offsets {+d, 0, -d} with weights {1, -2, 1}, as in newell_entry
+    // offsets {+d, 0, -d} with weights {1, -2, 1}, as in k_tensor_near
     const int oi[3] = {1, 0, -1};
     const double w3[3] = {1.0, -2.0, 1.0};
     const double pref = -1.0 / (4.0 * M_PI * dx * dy);

@@ -37,6 +37,29 @@ def test_real_tensor_matches_oracle_near_and_far():
     plan.destroy()
 
 
+@pytest.mark.parametrize("shape", [(400, 9), (9, 400)])
+def test_real_tensor_far_tiers_match_oracle(shape):
+    """Lattices 800 nm long in x or in y: the entries run through every
+    quadrature tier up to the 2-point rule (rho >= 100), checked element by
+    element against the oracle's table (3 points per axis in extended
+    precision beyond 50 cell sizes)."""
+    nx, ny = shape
+    wl = W.small_case(nx, ny, 3, seed=111, dx=2.0, dy=2.0)
+    plan = plan_for(wl)
+    t, zb = wl.thickness[0], wl.z_bottom[0]
+    for (i, j) in [(0, 0), (0, 2), (2, 1)]:
+        got = plan.export_real_tensor(i, j)
+        ref = oracle.pair_table(wl.nx, wl.ny, wl.dx, wl.dy, zb[i], zb[i] + t[i], zb[j], zb[j] + t[j])
+        scale = np.abs(ref).max()
+        diff = np.abs(got - ref)
+        assert diff.max() < 2e-9 * scale, (i, j, diff.max() / scale)
+        assert np.all(diff <= 1e-8 * np.abs(ref) + 1e-12 * scale), (i, j)
+        # the far end of the lattice lies beyond 100 cell sizes
+        dmax = max(wl.dx, wl.dy, t[i], t[j])
+        assert (max(nx, ny) - 1) * 2.0 / dmax > 100
+    plan.destroy()
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_fourier_tensor_matches_oracle(fp64):
     wl = W.small_case(12, 9, 3, seed=102)
