@@ -69,7 +69,9 @@ enum {
                                    between hfd_demag_vjp calls: one table over the
                                    distinct |interface offsets| of all stacks, built
                                    by setup / hfd_set_thickness (default: rebuilt
-                                   per stack inside every call)                       */
+                                   inside every call for groups of consecutive
+                                   stacks whose shared table holds at most 256 MiB
+                                   of spectra, or one stack's table if larger)        */
     HFD_MIX_BATCHED_FP32 = 16,  /* five-pass path with the batched (16 states per
                                    block) FP32 VALU mixing, the FP32 twin of
                                    HFD_MIX_SPLIT_BF16                                 */

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -172,7 +173,8 @@ struct hfd_plan_s {
     int itab_stride = 0;
     double* zeta_dev = nullptr; // [tables][nzeta_max]
     int nzeta_max = 0;
-    std::vector<int> nzeta;     // per table (one shared table when stored, else per stack)
+    std::vector<int> nzeta;     // per table (one shared table when stored, else per group)
+    std::vector<int> dgroup;    // first stack of each table's group, then G
     std::vector<double> zeta_host;
     std::vector<int> itab_host;
     bool d_valid = false;       // D holds the current geometry (stored mode)
@@ -553,8 +555,69 @@ hfd_status check_equidistant(int nz, int G, const std::vector<double>& t, const 
 // positions (top_l and bot_{l+1} merged when they touch), their ranks, the
 // position of every layer's bottom and top, and for every position pair the
 // D slot of |z_p - z_q| times 2, plus 1 when z_p < z_q.
-void derivative_offsets(hfd_plan p, bool shared, std::vector<double>& zeta, std::vector<int>& itab,
-                        std::vector<int>& count, int& nmax)
+// sorted distinct |offsets| of stacks g0 .. g1-1 (the four interface
+// differences of every ordered layer pair), values within rounding of zero
+// snapped to exactly zero (touching interfaces)
+static std::vector<double> distinct_offsets(hfd_plan p, int g0, int g1)
+{
+    const int nz = p->nz;
+    std::vector<double> u;
+    double sc = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const double* t = &p->thick[(size_t)g * nz];
+        const double* z = &p->zbot[(size_t)g * nz];
+        for (int l = 0; l < nz; ++l) sc = std::max(sc, std::fabs(z[l]) + t[l]);
+        for (int i = 0; i < nz; ++i)
+            for (int j = 0; j < nz; ++j) {
+                const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
+                u.insert(u.end(), {std::fabs(ti - bj), std::fabs(bi - bj), std::fabs(ti - tj),
+                                   std::fabs(bi - tj)});
+            }
+    }
+    std::sort(u.begin(), u.end());
+    std::vector<double> m;
+    for (double v : u) {
+        if (!m.empty() && std::fabs(v - m.back()) <= 1e-12 * std::max(1.0, std::fabs(v))) continue;
+        m.push_back(v);
+    }
+    for (double& v : m)
+        if (std::fabs(v) <= 1e-12 * std::max(1.0, sc)) v = 0.0;
+    return m;
+}
+
+// Groups of consecutive stacks that share one offset table: all stacks in one
+// group when stored; otherwise stacks are added to a group while the union of
+// their offsets stays within cap slots (a stack alone may exceed it).
+// Returns the first stack of every group, then G.
+static std::vector<int> derivative_groups(hfd_plan p, bool shared, int cap)
+{
+    std::vector<int> first{0};
+    if (!shared) {
+        std::vector<double> cur;
+        for (int g = 0; g < p->G; ++g) {
+            const std::vector<double> own = distinct_offsets(p, g, g + 1);
+            std::vector<double> merged;
+            std::merge(cur.begin(), cur.end(), own.begin(), own.end(), std::back_inserter(merged));
+            std::vector<double> m;
+            for (double v : merged)
+                if (m.empty() || std::fabs(v - m.back()) > 1e-12 * std::max(1.0, std::fabs(v)))
+                    m.push_back(v);
+            if (g > first.back() && (int)m.size() > cap) {
+                first.push_back(g);
+                cur = own;
+            } else {
+                cur.swap(m);
+            }
+        }
+    }
+    first.push_back(p->G);
+    return first;
+}
+
+// Offset tables of the groups `first` and the interface table itab of every
+// stack, whose pair entries index its group's table.
+void derivative_offsets(hfd_plan p, const std::vector<int>& first, std::vector<double>& zeta,
+                        std::vector<int>& itab, std::vector<int>& count, int& nmax)
 {
     const int nz = p->nz, G = p->G;
     const ITabLayout lay = itab_layout(nz);
@@ -571,41 +634,16 @@ void derivative_offsets(hfd_plan p, bool shared, std::vector<double>& zeta, std:
         for (int l = 0; l < nz; ++l) sc = std::max(sc, std::fabs(z[l]) + t[l]);
         return sc;
     };
-    // sorted distinct |offsets| of stacks g0 .. g1-1, values within rounding of
-    // zero snapped to exactly zero (touching interfaces)
-    auto offsets = [&](int g0, int g1) {
-        std::vector<double> u;
-        double sc = 0.0;
-        for (int g = g0; g < g1; ++g) {
-            const double *t, *z;
-            geo(g, t, z);
-            sc = std::max(sc, scale_of(g));
-            for (int i = 0; i < nz; ++i)
-                for (int j = 0; j < nz; ++j) {
-                    const double ti = z[i] + t[i], bi = z[i], tj = z[j] + t[j], bj = z[j];
-                    u.insert(u.end(), {std::fabs(ti - bj), std::fabs(bi - bj), std::fabs(ti - tj),
-                                       std::fabs(bi - tj)});
-                }
-        }
-        std::sort(u.begin(), u.end());
-        std::vector<double> m;
-        for (double v : u) {
-            if (!m.empty() && std::fabs(v - m.back()) <= 1e-12 * std::max(1.0, std::fabs(v))) continue;
-            m.push_back(v);
-        }
-        for (double& v : m)
-            if (std::fabs(v) <= 1e-12 * std::max(1.0, sc)) v = 0.0;
-        return m;
-    };
-    // one table for every stack (shared) or one per stack
     std::vector<std::vector<double>> tables;
-    if (shared) tables.push_back(offsets(0, G));
-    else
-        for (int g = 0; g < G; ++g) tables.push_back(offsets(g, g + 1));
+    std::vector<int> table_of((size_t)G);
+    for (size_t k = 0; k + 1 < first.size(); ++k) {
+        tables.push_back(distinct_offsets(p, first[k], first[k + 1]));
+        for (int g = first[k]; g < first[k + 1]; ++g) table_of[(size_t)g] = (int)k;
+    }
     for (int g = 0; g < G; ++g) {
         const double *t, *z;
         geo(g, t, z);
-        const std::vector<double>& m = tables[shared ? 0 : g];
+        const std::vector<double>& m = tables[(size_t)table_of[(size_t)g]];
         const double ztol = 1e-12 * std::max(1.0, scale_of(g));
         auto nearest = [&](double v) {
             const auto it = std::lower_bound(m.begin(), m.end(), v);
@@ -653,6 +691,9 @@ void derivative_offsets(hfd_plan p, bool shared, std::vector<double>& zeta, std:
         for (int i = 0; i < count[k]; ++i) zeta[(size_t)k * nmax + i] = tables[k][i];
 }
 
+// derivative spectra one recomputed table may hold (see setup_derivatives)
+constexpr long long kRecomputeBytes = 256LL << 20;
+
 // Allocate (or grow) the derivative buffers and upload the offsets.  New
 // buffers are allocated before the old ones are released, so a failure leaves
 // the previous buffers in place (the plan is then marked not ready by the
@@ -663,9 +704,16 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     std::vector<double> zeta;
     std::vector<int> itab, count;
     int nmax = 0;
-    // stored: one table shared by all stacks; recomputed: one table per stack,
-    // built into the same buffer before that stack's reduction
-    derivative_offsets(p, (p->flags & HFD_STORE_DTENSOR) != 0, zeta, itab, count, nmax);
+    // stored: one table shared by all stacks; recomputed: one table per group
+    // of stacks, built into the same buffer before that group's reduction.  A
+    // group's table holds up to kRecomputeBytes of spectra (or one stack's
+    // table where that is larger): neighbouring stacks (thickness candidates)
+    // share most offsets, and each shared offset is built once per group.
+    const bool stored = (p->flags & HFD_STORE_DTENSOR) != 0;
+    const long long slot_bytes = 6LL * p->QX * p->QY * p->rsz;
+    const int cap = (int)std::max(1LL, kRecomputeBytes / slot_bytes);
+    const std::vector<int> first = derivative_groups(p, stored, cap);
+    derivative_offsets(p, first, zeta, itab, count, nmax);
     auto swap_in = [](auto*& slot, auto* fresh) {
         if (slot) (void)hipFree(slot);
         slot = fresh;
@@ -712,6 +760,7 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
         for (int i = 0; i < count[k]; ++i) p->zeta_host[k * p->nzeta_max + i] = zeta[k * nmax + i];
     p->itab_host = itab;
     p->nzeta = count;
+    p->dgroup = first;
     HFD_HIP(hipMemcpyAsync(p->zeta_dev, p->zeta_host.data(), sizeof(double) * p->zeta_host.size(),
                            hipMemcpyHostToDevice, s));
     HFD_HIP(hipMemcpyAsync(p->itab, p->itab_host.data(), sizeof(int) * itab.size(),
@@ -1152,12 +1201,13 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
                              p->D, p->nzeta_max, p->itab, p->itab_stride, p->lp, bpg, p->QX, p->QY,
                              p->partial, s));
     } else {
-        // recompute the derivative tensor of one stack at a time
-        for (int g = 0; g < p->G; ++g) {
-            HFD_TRY(compute_derivatives(p, g, s));
-            HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g * bpg, bpg, p->Q,
-                                 p->q_geom_stride, p->D, p->nzeta_max, p->itab, p->itab_stride,
-                                 p->lp, bpg, p->QX, p->QY, p->partial, s));
+        // recompute the derivative tensor of one group of stacks at a time
+        for (size_t k = 0; k + 1 < p->dgroup.size(); ++k) {
+            const int g0 = p->dgroup[k], g1 = p->dgroup[k + 1];
+            HFD_TRY(compute_derivatives(p, (int)k, s));
+            HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g0 * bpg, (g1 - g0) * bpg,
+                                 p->Q, p->q_geom_stride, p->D, p->nzeta_max, p->itab,
+                                 p->itab_stride, p->lp, bpg, p->QX, p->QY, p->partial, s));
         }
     }
     HFD_HIP(launch_tgrad_finish(p->partial, p->ntiles, batch, p->nz, p->itab, p->itab_stride, bpg,
