@@ -6,7 +6,7 @@
 // product.  Written as a real product
 //      [Hr]   [Sr  -Si] [Mr]
 //      [Hi] = [Si   Sr] [Mi]      (6nz x 6nz) x (6nz x states)
-// it runs on v_mfma_f32_16x16x16_bf16 with both operands split into three
+// it runs on v_mfma_f32_16x16x32_bf16 with both operands split into three
 // BF16 terms (a = a0 + a1 + a2, each the BF16 rounding of the remainder) and
 // the six products of combined order <= 2 accumulated in FP32, which keeps
 // about 24 bits per product.  A block owns 16 (8 above five layers)
@@ -24,7 +24,7 @@ namespace hfd {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NBS = 16;      // states per chunk (the 16 columns of one product)
@@ -39,15 +39,15 @@ __device__ __forceinline__ unsigned short bf16_bits(float x)
 }
 __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-__device__ __forceinline__ void split3(float x, short& h, short& m, short& l)
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l)
 {
     const unsigned short bh = bf16_bits(x);
     const float r1 = x - bf16_float(bh);
     const unsigned short bm = bf16_bits(r1);
     const float r2 = r1 - bf16_float(bm);
-    h = (short)bh;
-    m = (short)bm;
-    l = (short)bf16_bits(r2);
+    h = __builtin_bit_cast(__bf16, bh);
+    m = __builtin_bit_cast(__bf16, bm);
+    l = __builtin_bit_cast(__bf16, bf16_bits(r2));
 }
 
 }  // namespace
@@ -55,8 +55,9 @@ __device__ __forceinline__ void split3(float x, short& h, short& m, short& l)
 template <int NZ>
 struct BatchedShape {
     static constexpr int S = 3 * NZ, S6 = 6 * NZ, P = NZ * (NZ + 1) / 2;
-    static constexpr int KT = (S6 + 15) / 16;       // 16-wide tiles of rows and of the sum
-    static constexpr int TK = NZ <= 5 ? 16 : 8;       // frequencies per block
+    static constexpr int KT = (S6 + 15) / 16;       // 16-row tiles (rows of A and of the output)
+    static constexpr int KT2 = (S6 + 31) / 32;      // 32-wide tiles of the sum (one product)
+    static constexpr int TK = 8;                      // frequencies per block
     static constexpr int FW = TK / 4;                 // frequencies per wave
     static constexpr int AS = (S6 + 3) & ~3;          // row stride of the FP32 matrix
     static constexpr size_t sm_bytes = sizeof(cpx<float>) * TK * S * NBS;
@@ -109,8 +110,8 @@ __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restric
                                                      int adjoint)
 {
     using SH = BatchedShape<NZ>;
-    constexpr int S = SH::S, S6 = SH::S6, P = SH::P, KT = SH::KT, TK = SH::TK, FW = SH::FW,
-                  AS = SH::AS;
+    constexpr int S = SH::S, S6 = SH::S6, P = SH::P, KT = SH::KT, KT2 = SH::KT2, TK = SH::TK,
+                  FW = SH::FW, AS = SH::AS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<float>* sm = reinterpret_cast<cpx<float>*>(smem_raw);                      // [TK][S][NBS]
     float* st = reinterpret_cast<float*>(smem_raw + SH::sm_bytes);                 // [TK][P][5]
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restric
     __syncthreads();
 
     const float* lpg = lp + (long long)geom * 2 * NZ;
-    bf16x4 ah[MFMA ? FW : 1][KT][KT], am[MFMA ? FW : 1][KT][KT], al[MFMA ? FW : 1][KT][KT];
+    bf16x8 ah[MFMA ? FW : 1][KT][KT2], am[MFMA ? FW : 1][KT][KT2], al[MFMA ? FW : 1][KT][KT2];
 #pragma unroll
     for (int f = 0; f < FW; ++f) {
         const int kyl = w + 4 * f;
@@ -147,17 +148,17 @@ __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restric
         build_real_matrix<NZ>(A, st + kyl * P * 5, lpg, l, adjoint);
         if constexpr (MFMA) {
             wave_sync();
-            // A operand layout of the 16x16x16 product: lane l holds row l % 16,
-            // sum indices 4 (l / 16) + e
+            // A operand layout of the 16x16x32 product: lane l holds row l % 16,
+            // sum indices 8 (l / 16) + e
 #pragma unroll
             for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
-                for (int kt = 0; kt < KT; ++kt)
+                for (int kt = 0; kt < KT2; ++kt)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = mt * 16 + (l & 15), k = kt * 16 + 4 * q4 + e;
+                    for (int e = 0; e < 8; ++e) {
+                        const int r = mt * 16 + (l & 15), k = kt * 32 + 8 * q4 + e;
                         const float v = (r < S6 && k < S6) ? A[r * AS + k] : 0.f;
-                        short h, m, lo;
+                        __bf16 h, m, lo;
                         split3(v, h, m, lo);
                         ah[f][mt][kt][e] = h;
                         am[f][mt][kt][e] = m;
@@ -189,31 +190,31 @@ __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restric
 #pragma unroll
                 for (int mt = 0; mt < KT; ++mt) D[mt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kt = 0; kt < KT; ++kt) {
-                    // B operand: lane l holds sum indices 4 (l / 16) + e of state l % 16
-                    bf16x4 bh, bm, bl;
+                for (int kt = 0; kt < KT2; ++kt) {
+                    // B operand: lane l holds sum indices 8 (l / 16) + e of state l % 16
+                    bf16x8 bh, bm, bl;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k = kt * 16 + 4 * q4 + e;
+                    for (int e = 0; e < 8; ++e) {
+                        const int k = kt * 32 + 8 * q4 + e;
                         float v = 0.f;
                         if (k < S6) {
                             const int pk = k / S, s = k - pk * S;
                             const cpx<float> z = mk[s * NBS + n];
                             v = pk == 0 ? z.x : z.y;
                         }
-                        short h, m, lo;
+                        __bf16 h, m, lo;
                         split3(v, h, m, lo);
                         bh[e] = h; bm[e] = m; bl[e] = lo;
                     }
 #pragma unroll
                     for (int mt = 0; mt < KT; ++mt) {
                         f32x4 d = D[mt];
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[f][mt][kt], bh, d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[f][mt][kt], bm, d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[f][mt][kt], bl, d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[f][mt][kt], bh, d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[f][mt][kt], bm, d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[f][mt][kt], bh, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f][mt][kt], bh, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f][mt][kt], bm, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f][mt][kt], bl, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f][mt][kt], bh, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f][mt][kt], bm, d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f][mt][kt], bh, d, 0, 0, 0);
                         D[mt] = d;
                     }
                 }
