@@ -208,6 +208,7 @@ struct hfd_plan_s {
     void* spg = nullptr;        // pair geometries
     double* sscale = nullptr;   // per pair scale
     double* sQ2 = nullptr;      // equidistant plans: per-offset spectra
+    int* spmap = nullptr;       // per setup chunk and pair: the pair's spectra in the chunk, or -1
     int schunk = 0, spg_cap = 0;
 };
 
@@ -300,7 +301,7 @@ void free_plan_memory(hfd_plan p)
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
                     p->D, p->itab, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz,
-                    p->sW, p->sF, p->spg, p->sscale, p->sQ2};
+                    p->sW, p->sF, p->spg, p->sscale, p->sQ2, p->spmap};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
@@ -318,6 +319,7 @@ void free_plan_memory(hfd_plan p)
     p->spg = nullptr;
     p->sscale = nullptr;
     p->sQ2 = nullptr;
+    p->spmap = nullptr;
 }
 
 // twiddle table exp(-2 pi i m / L), m in [0, L), in FP64 (exact octant reduction)
@@ -381,10 +383,19 @@ hfd_status alloc_setup_scratch(hfd_plan p)
     HFD_TRY(dev_alloc(&p->sF, (size_t)p->schunk * per_pair, "tensor setup (spectra)"));
     HFD_TRY(dev_alloc(&p->spg, sizeof(PairGeoH) * (size_t)ngeo, "pair table"));
     HFD_TRY(dev_alloc(&p->sscale, sizeof(double) * (size_t)ngeo, "pair scales"));
+    const int nchunks = (ngeo + p->schunk - 1) / p->schunk;
+    HFD_TRY(dev_alloc(&p->spmap, sizeof(int) * (size_t)p->P * nchunks, "pair map"));
     if (p->eq3d)
         HFD_TRY(dev_alloc(&p->sQ2, sizeof(double) * 6 * (size_t)p->QX * p->QY * (2 * p->nz - 1),
                           "per-offset spectra"));
     return HFD_OK;
+}
+
+static double max_thickness(const std::vector<PairGeoH>& geos, int first, int count)
+{
+    double t = 0.0;
+    for (int u = first; u < first + count; ++u) t = std::max(t, std::max(geos[u].ti, geos[u].tj));
+    return t;
 }
 
 // FP64 2D spectra (x and y transforms of the zero-padded real-space tensor,
@@ -392,12 +403,6 @@ hfd_status alloc_setup_scratch(hfd_plan p)
 // plan's setup scratch; after each chunk pack(first, count, F) enqueues the
 // packing of spectra F[count][6][M][Ly] (complex, interleaved re/im doubles).
 // Synchronizes the stream at the end.
-static double max_thickness(const std::vector<PairGeoH>& geos, int first, int count)
-{
-    double t = 0.0;
-    for (int u = first; u < first + count; ++u) t = std::max(t, std::max(geos[u].ti, geos[u].tj));
-    return t;
-}
 
 template <class Pack>
 hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
@@ -413,7 +418,8 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
     hipError_t e = hipMemcpyAsync(pg, geos.data(), sizeof(PairGeoH) * n, hipMemcpyHostToDevice, s);
     for (int u0 = 0; u0 < n && e == hipSuccess; u0 += CP) {
         const int np = std::min(CP, n - u0);
-        e = hipMemsetAsync(W, 0, (size_t)np * per_pair, s);
+        // the lattice kernels write every entry of the quadrant and its images
+        e = launch_zero_gaps(W, (long long)np * 6, p->nx, p->ny, p->Lx, p->Ly, s);
         if (e == hipSuccess)
             e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy,
                                    max_thickness(geos, u0, np), 0, s);
@@ -437,7 +443,7 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
     double* scale = p->sscale;
     hfd_status st = HFD_OK;
     std::vector<PairGeoH> ug;
-    std::vector<int> uid((size_t)p->P);
+    std::vector<int> uid((size_t)p->P), pmap;
     std::vector<double> hs((size_t)p->P);
     for (int g = 0; g < p->G && st == HFD_OK; ++g) {
         const double* t = &p->thick[(size_t)g * p->nz];
@@ -461,16 +467,20 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
             break;
         }
         char* qdst = (char*)p->Q + (size_t)g * p->q_geom_stride * p->rsz;
-        const size_t fstride = (size_t)2 * 6 * p->M * p->Ly;  // doubles per geometry
+        // per setup chunk: which of its spectra each pair takes (pairs with the
+        // same geometry share one), packed by one launch per chunk
+        const int CP = p->schunk, nch = ((int)ug.size() + CP - 1) / CP;
+        pmap.assign((size_t)nch * p->P, -1);
+        for (int pu = 0; pu < p->P; ++pu) pmap[(size_t)(uid[pu] / CP) * p->P + pu] = uid[pu] % CP;
+        if (hipMemcpyAsync(p->spmap, pmap.data(), sizeof(int) * pmap.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess) {
+            st = fail(HFD_EHIP, "tensor setup: pair map upload failed");
+            break;
+        }
         st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
-            for (int pu = 0; pu < p->P; ++pu) {
-                const int k = uid[pu];
-                if (k < u0 || k >= u0 + np) continue;
-                hipError_t e = launch_pack(p->fp64, F + (size_t)(k - u0) * fstride, qdst, scale + pu, 1, 5,
-                                           p->M, p->Ly, p->QX, p->QY, pu, p->P, 1, s);
-                if (e != hipSuccess) return e;
-            }
-            return hipSuccess;
+            (void)np;
+            return launch_pack(p->fp64, F, qdst, scale, p->P, 5, p->M, p->Ly, p->QX, p->QY, 0, p->P, 1,
+                               s, p->spmap + (size_t)(u0 / CP) * p->P);
         });
     }
     (void)hipStreamSynchronize(s);

@@ -140,9 +140,11 @@ hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx
 hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
                                int Ly, double dx, double dy, hipStream_t s);
 // comps 5: field tensor, written at pairs pair0.. of a [QX][pair_total][5][QY] array;
-// comps 6: derivative tables, [npairs][6][QX][QY]
+// comps 6: derivative tables, [npairs][6][QX][QY].  src (device, optional): for
+// output pair u the index of its spectra in F, or -1 to leave the pair alone
+// (default: u itself).
 hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
                        int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
-                       int row_outer, hipStream_t s);
+                       int row_outer, hipStream_t s, const int* src = nullptr);
 
 }  // namespace hfd

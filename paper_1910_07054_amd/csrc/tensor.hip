@@ -48,7 +48,7 @@ hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx,
 
 hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
                        int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
-                       int row_outer, hipStream_t s)
+                       int row_outer, hipStream_t s, const int* src)
 {
     const long long n = (long long)npairs * comps * QX * QY;
     const long long nb = (n + 255) / 256;
@@ -56,11 +56,11 @@ hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scal
     if (out_fp64)
         hipLaunchKernelGGL(k_pack<double>, dim3((unsigned)nb), dim3(256), 0, s,
                            (const cpx<double>*)F, (double*)Q, scale, npairs, comps, M, Ly, QX, QY, pair0, pair_total,
-                           row_outer);
+                           row_outer, src);
     else
         hipLaunchKernelGGL(k_pack<float>, dim3((unsigned)nb), dim3(256), 0, s,
                            (const cpx<double>*)F, (float*)Q, scale, npairs, comps, M, Ly, QX, QY, pair0, pair_total,
-                           row_outer);
+                           row_outer, src);
     return hipGetLastError();
 }
 

@@ -557,17 +557,20 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F, R* __restrict__ Qout,
                                               const double* __restrict__ scale, int npairs, int comps,
                                               int M, int Ly, int QX, int QY, int pair0,
-                                              int pair_total, int row_outer)
+                                              int pair_total, int row_outer,
+                                              const int* __restrict__ src)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)comps * QX * QY;
     if (idx >= per * npairs) return;
     const int u = (int)(idx / per);
+    const int su = src ? src[u] : u;  // this pair's spectra in F
+    if (su < 0) return;
     const long long rem = idx % per;
     const int c = (int)(rem / ((long long)QX * QY));
     const int kx = (int)((rem / QY) % QX), ky = (int)(rem % QY);
     const int c6 = comps == 5 ? (c < 2 ? c : c + 1) : c;
-    const cpx<double>* Fs = F + ((long long)u * 6 + c6) * M * Ly;
+    const cpx<double>* Fs = F + ((long long)su * 6 + c6) * M * Ly;
     cpx<double> val;
     if (kx == 0 || kx == M) {
         const cpx<double> z1 = Fs[ky], z2 = Fs[(Ly - ky) & (Ly - 1)];
