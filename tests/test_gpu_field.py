@@ -60,6 +60,63 @@ def test_real_tensor_far_tiers_match_oracle(shape):
     plan.destroy()
 
 
+def test_real_tensor_thick_layers_on_fine_cells_match_oracle():
+    """Layers thicker than the cells (3.1 and 2.7 nm on 1.0 x 0.7 nm cells): the
+    largest cell dimension is a thickness, so the boxes that hold the 64-term
+    entries (rho < 6) and the 16-lane quadrature entries (rho < 32) are sized
+    by it.  The 64-term sum loses digits as R^6 / (dx^2 dy^2 t_i t_j): the
+    oracle's extended-precision table about 1e-9 at 16 largest-cell sizes for
+    these cells and 1e-6 at 49 (where its own switch to quadrature lies), so
+    the whole table is compared out to 16 sizes and beyond that sampled
+    entries against the oracle's 12-point Gauss-Legendre rule over both
+    cuboids.  The GPU's FP64 sum loses up to 8e-6 of small entries just inside
+    rho = 6 for cells this flat (at most 9e-11 of the largest entry, the thin
+    0.5 nm target layer against the 3.1 nm source); the per-entry bound is
+    1e-6 of the entry plus 2e-10 of the largest one here, 1e-8 of the entry
+    for cells of comparable sides (the tests above)."""
+    from paper_1910_07054_amd.workloads import Workload, stack_bottoms
+    t = np.array([3.1, 2.7, 0.5])
+    zb = stack_bottoms(t, [0.2, 0.0])
+    nx, ny = 150, 170
+    wl = Workload("thick", nx, ny, 1.0, 0.7, t[None], zb[None], np.zeros((1, 3, 3, ny, nx)), 0)
+    plan = plan_for(wl)
+    rng = np.random.default_rng(17)
+    for (i, j) in [(0, 0), (0, 1), (1, 2), (2, 0)]:
+        got = plan.export_real_tensor(i, j)
+        # entries out to 16 largest-cell sizes: the oracle's table
+        n1x, n1y = 36, 50
+        ref = oracle.pair_table(n1x, n1y, wl.dx, wl.dy, zb[i], zb[i] + t[i], zb[j], zb[j] + t[j])
+        sub = got[:, ny - n1y:ny + n1y - 1, nx - n1x:nx + n1x - 1]
+        scale = np.abs(ref).max()
+        diff = np.abs(sub - ref)
+        assert diff.max() < 2e-9 * scale, (i, j, diff.max() / scale)
+        excess = diff - (1e-6 * np.abs(ref) + 2e-10 * scale)
+        if np.any(excess > 0):
+            rows = []
+            for f in np.argsort(excess.ravel())[::-1][:5]:
+                c, qi, pi = np.unravel_index(f, excess.shape)
+                p_, q_ = pi - (n1x - 1), qi - (n1y - 1)
+                rho = np.sqrt((p_ * wl.dx) ** 2 + (q_ * wl.dy) ** 2 + (zb[i] - zb[j] + 0.5 * (t[i] - t[j])) ** 2)
+                rows.append((int(c), int(p_), int(q_), round(float(rho / max(wl.dx, wl.dy, t[i], t[j])), 2),
+                             float(diff[c, qi, pi] / scale), float(ref[c, qi, pi] / scale)))
+            raise AssertionError(f"pair {(i, j)}: (comp, p, q, rho, err/scale, ref/scale) {rows}")
+        # farther entries, 20 to 60 sizes: the oracle's quadrature, one by one
+        dmax = max(wl.dx, wl.dy, t[i], t[j])
+        zc = zb[i] - zb[j] + 0.5 * (t[i] - t[j])
+        checked = 0
+        while checked < 6:
+            p_, q_ = int(rng.integers(-(nx - 1), nx)), int(rng.integers(-(ny - 1), ny))
+            rho = np.sqrt((p_ * wl.dx) ** 2 + (q_ * wl.dy) ** 2 + zc ** 2) / dmax
+            if not 20.0 <= rho <= 60.0:
+                continue
+            e = oracle.quad_tensor(p_ * wl.dx, q_ * wl.dy, zb[i] - zb[j], (wl.dx, wl.dy, t[i]),
+                                   (wl.dx, wl.dy, t[j]), n=12)
+            g = got[:, q_ + ny - 1, p_ + nx - 1]
+            assert np.all(np.abs(g - e) <= 1e-9 * np.abs(e) + 1e-13 * scale), (i, j, p_, q_, rho)
+            checked += 1
+    plan.destroy()
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_fourier_tensor_matches_oracle(fp64):
     wl = W.small_case(12, 9, 3, seed=102)
