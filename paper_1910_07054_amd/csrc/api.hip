@@ -398,11 +398,11 @@ static double max_thickness(const std::vector<PairGeoH>& geos, int first, int co
     return t;
 }
 
-// FP64 2D spectra (x and y transforms of the zero-padded real-space tensor,
-// 6 components each) of the cuboid-pair geometries `geos`, in chunks of the
-// plan's setup scratch; after each chunk pack(first, count, F) enqueues the
-// packing of spectra F[count][6][M][Ly] (complex, interleaved re/im doubles).
-// Synchronizes the stream at the end.
+// FP64 x-pass spectra of the zero-padded real-space tensor (6 components
+// each) of the cuboid-pair geometries `geos`, in chunks of the plan's setup
+// scratch; after each chunk pack(first, count, F) enqueues the y transforms
+// and packing (launch_ytab) of spectra F[count][6][M][Ly] (complex,
+// interleaved re/im doubles).  Synchronizes the stream at the end.
 
 template <class Pack>
 hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
@@ -425,8 +425,6 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
                                    max_thickness(geos, u0, np), 0, s);
         if (e == hipSuccess)
             e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
-        if (e == hipSuccess)
-            e = launch_yfwd(true, p->Ly, F, F, p->Ly, (long long)np * 6 * p->M, p->twy64, s);
         if (e == hipSuccess) e = pack(u0, np, (const double*)F);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -479,8 +477,8 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
         }
         st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
             (void)np;
-            return launch_pack(p->fp64, F, qdst, scale, p->P, 5, p->M, p->Ly, p->QX, p->QY, 0, p->P, 1,
-                               s, p->spmap + (size_t)(u0 / CP) * p->P);
+            return launch_ytab(p->fp64, F, qdst, scale, p->P, 5, p->M, p->Ly, p->QX, p->QY, 0, p->P, 1,
+                               p->twy64, s, p->spmap + (size_t)(u0 / CP) * p->P);
         });
     }
     (void)hipStreamSynchronize(s);
@@ -527,8 +525,8 @@ hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
         st = fail(HFD_EHIP, "tensor setup: scale upload failed");
     if (st == HFD_OK)
         st = tensor_spectra(p, geos, s, [&](int u0, int np, const double* F) -> hipError_t {
-            return launch_pack(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->Ly, p->QX,
-                               p->QY, 0, np, 0, s);
+            return launch_ytab(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->Ly, p->QX,
+                               p->QY, 0, np, 0, p->twy64, s);
         });
     if (st == HFD_OK) {
         hipError_t e = launch_zdft3(p->fp64, Q2, p->Q, p->nz, p->Lz, p->QX, p->QY, s);
@@ -803,9 +801,8 @@ hfd_status compute_derivatives(hfd_plan p, int g, hipStream_t s)
         HFD_HIP(launch_dtensor_real(p->dW, p->zeta_dev + (size_t)g * p->nzeta_max + z0, nc, p->nx,
                                     p->ny, p->Lx, p->Ly, p->dx, p->dy, s));
         HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));
-        HFD_HIP(launch_yfwd(true, p->Ly, p->dF, p->dF, p->Ly, (long long)nc * 6 * p->M, p->twy64, s));
-        HFD_HIP(launch_pack(p->fp64, p->dF, dst, p->dscale, nc, 6, p->M, p->Ly, p->QX, p->QY, z0,
-                            p->nzeta_max, 1, s));
+        HFD_HIP(launch_ytab(p->fp64, p->dF, dst, p->dscale, nc, 6, p->M, p->Ly, p->QX, p->QY, z0,
+                            p->nzeta_max, 1, p->twy64, s));
     }
     return HFD_OK;
 }

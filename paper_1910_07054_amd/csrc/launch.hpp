@@ -139,12 +139,14 @@ hipError_t launch_zero64(double* p, long long n, hipStream_t s);
 hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx, int Ly, hipStream_t s);
 hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
                                int Ly, double dx, double dy, hipStream_t s);
-// comps 5: field tensor, written at pairs pair0.. of a [QX][pair_total][5][QY] array;
-// comps 6: derivative tables, [npairs][6][QX][QY].  src (device, optional): for
-// output pair u the index of its spectra in F, or -1 to leave the pair alone
-// (default: u itself).
-hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
+// y transforms of x-pass tensor spectra F[pair][6][M][Ly] (FP64) and their
+// packing into the quadrant: comps 5 (field tensor) or 6 (all components);
+// row_outer: [QX][pair_total][comps][QY] at pairs pair0.., else
+// [npairs][comps][QX][QY]; times scale[u].  src (device, optional): for output
+// pair u the index of its spectra in F, or -1 to leave the pair alone
+// (default: u itself).  twy64: the FP64 twiddles of length Ly.
+hipError_t launch_ytab(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
                        int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
-                       int row_outer, hipStream_t s, const int* src = nullptr);
+                       int row_outer, const void* twy64, hipStream_t s, const int* src = nullptr);
 
 }  // namespace hfd

@@ -46,22 +46,46 @@ hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx,
     return hipGetLastError();
 }
 
-hipError_t launch_pack(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
-                       int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
-                       int row_outer, hipStream_t s, const int* src)
+template <typename R, int LY>
+static hipError_t ytab_t(const void* F, void* Q, const double* scale, int npairs, int comps, int M,
+                         int QX, int QY, int pair0, int pair_total, int row_outer, const int* src,
+                         const void* twy, hipStream_t s)
 {
-    const long long n = (long long)npairs * comps * QX * QY;
-    const long long nb = (n + 255) / 256;
+    using S = TabShape<LY>;
+    const long long tasks = (long long)npairs * M * 3;
+    const long long nb = (tasks + S::NG - 1) / S::NG;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (out_fp64)
-        hipLaunchKernelGGL(k_pack<double>, dim3((unsigned)nb), dim3(256), 0, s,
-                           (const cpx<double>*)F, (double*)Q, scale, npairs, comps, M, Ly, QX, QY, pair0, pair_total,
-                           row_outer, src);
-    else
-        hipLaunchKernelGGL(k_pack<float>, dim3((unsigned)nb), dim3(256), 0, s,
-                           (const cpx<double>*)F, (float*)Q, scale, npairs, comps, M, Ly, QX, QY, pair0, pair_total,
-                           row_outer, src);
+    hipLaunchKernelGGL((k_ytab<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<double>*)F,
+                       (R*)Q, scale, npairs, comps, M, QX, QY, pair0, pair_total, row_outer, src,
+                       (const cpx<double>*)twy);
     return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t ytab_r(int Ly, const void* F, void* Q, const double* scale, int npairs, int comps,
+                         int M, int QX, int QY, int pair0, int pair_total, int row_outer,
+                         const int* src, const void* twy, hipStream_t s)
+{
+    switch (Ly) {
+#define HFD_YTAB(L) \
+    case L: return ytab_t<R, L>(F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total, row_outer, src, twy, s);
+    HFD_YTAB(8) HFD_YTAB(16) HFD_YTAB(32) HFD_YTAB(64) HFD_YTAB(128) HFD_YTAB(256) HFD_YTAB(512)
+    HFD_YTAB(1024) HFD_YTAB(2048) HFD_YTAB(4096)
+#undef HFD_YTAB
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ytab(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
+                       int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
+                       int row_outer, const void* twy64, hipStream_t s, const int* src)
+{
+    if (npairs <= 0) return hipSuccess;
+    if ((comps != 5 && comps != 6) || M < 1) return hipErrorInvalidValue;
+    return out_fp64 ? ytab_r<double>(Ly, F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total,
+                                     row_outer, src, twy64, s)
+                    : ytab_r<float>(Ly, F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total,
+                                    row_outer, src, twy64, s);
 }
 
 // Zero the entries of nplanes Lx x Ly planes that the lattice kernels leave

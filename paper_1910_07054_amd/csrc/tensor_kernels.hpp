@@ -545,45 +545,110 @@ __global__ __launch_bounds__(kDTile * kDTile) void k_dtensor_real(double* __rest
     }
 }
 
-// Pack the FP64 2D spectra F[nsig][M][Ly] (x pass packed, column 0 = kx 0 and
-// Lx/2) of arrays with the lateral parity of the tensor into the quadrant
-// kx in [0, M], ky in [0, Ly/2]: real part for the even-even and odd-odd
-// components, imaginary part for the odd-even ones, times scale[pair].
-// comps: number of stored components per pair (5: xx, yy, xy, xz, yz;
-// 6: all); the source has 6 arrays per pair in the order xx yy zz xy xz yz.
-// row_outer: output [kx][pair_total][comps][ky] with this call's pairs at
-// pair0 (each kx row of a table contiguous); else [pair][comp][kx][ky].
-template <typename R>
-__global__ __launch_bounds__(256) void k_pack(const cpx<double>* __restrict__ F, R* __restrict__ Qout,
-                                              const double* __restrict__ scale, int npairs, int comps,
-                                              int M, int Ly, int QX, int QY, int pair0,
-                                              int pair_total, int row_outer,
-                                              const int* __restrict__ src)
+// y transforms of the tensor tables and their packing, in one kernel.
+// Input: the x-pass spectra F[pair][6][M][Ly] (FP64, complex) of arrays with
+// the lateral parity of the tensor: xx, yy, zz even in x and y, xy odd in
+// both, xz odd in x, yz odd in y.  After the x transform a column kx >= 1 of
+// an x-even component is real and one of an x-odd component imaginary; the y
+// transform of a real y-even column is real, of a y-odd one imaginary.  Two
+// components whose column parts share the y parity therefore take one complex
+// transform of length Ly, z = a + i b, whose real and imaginary parts are the
+// two results (y odd: Z = i (A' + i B'), A' = Im Z, B' = -Re Z): the pairs
+// (xx, yy), (zz, xz) and (xy, yz), three transforms per column instead of six.
+// The packed column 0 holds kx = 0 in its real and kx = Lx/2 in its imaginary
+// part; there the x-odd components vanish and each x-even one is its own pair.
+// Output per component, as the quadrant kx in [0, M], ky in [0, Ly/2] of the
+// 2D transform: its real part for xx, yy, zz, xy, its imaginary part for xz,
+// yz (the non-zero one), times scale[pair].
+// comps: 5 (xx, yy, xy, xz, yz; zz follows from the trace) or 6 (all, in the
+// order xx yy zz xy xz yz); row_outer: output [kx][pair_total][comps][ky] with
+// this call's pairs at pair0, else [pair][comps][kx][ky].  src (optional): the
+// spectra of output pair u are F[src[u]], none if src[u] < 0.
+template <int LY>
+struct TabShape {
+    static constexpr int V = fft_vals(LY);
+    static constexpr int GT = LY / V;
+    static constexpr int NG0 = 256 / GT;
+    static constexpr int NGL = (int)(65536 / (sizeof(cpx<double>) * fft_region(LY)));
+    static constexpr int NG = NG0 < NGL ? NG0 : (NGL < 1 ? 1 : NGL);
+    static constexpr int NT = NG * GT;
+};
+
+template <typename R, int LY>
+__global__ __launch_bounds__((TabShape<LY>::NT)) void k_ytab(
+    const cpx<double>* __restrict__ F, R* __restrict__ Qout, const double* __restrict__ scale,
+    int npairs, int comps, int M, int QX, int QY, int pair0, int pair_total, int row_outer,
+    const int* __restrict__ src, const cpx<double>* __restrict__ twy)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)comps * QX * QY;
-    if (idx >= per * npairs) return;
-    const int u = (int)(idx / per);
-    const int su = src ? src[u] : u;  // this pair's spectra in F
+    using S = TabShape<LY>;
+    __shared__ cpx<double> sh[S::NG * fft_region(LY)];
+    const int grp = threadIdx.x / S::GT, g = threadIdx.x % S::GT;
+    const long long task = (long long)blockIdx.x * S::NG + grp;
+    if (task >= (long long)npairs * M * 3) return;
+    const int k = (int)(task % 3);
+    const int kxc = (int)((task / 3) % M);
+    const int u = (int)(task / (3LL * M));
+    const int su = src ? src[u] : u;
     if (su < 0) return;
-    const long long rem = idx % per;
-    const int c = (int)(rem / ((long long)QX * QY));
-    const int kx = (int)((rem / QY) % QX), ky = (int)(rem % QY);
-    const int c6 = comps == 5 ? (c < 2 ? c : c + 1) : c;
-    const cpx<double>* Fs = F + ((long long)su * 6 + c6) * M * Ly;
-    cpx<double> val;
-    if (kx == 0 || kx == M) {
-        const cpx<double> z1 = Fs[ky], z2 = Fs[(Ly - ky) & (Ly - 1)];
-        if (kx == 0) val = {0.5 * (z1.x + z2.x), 0.5 * (z1.y - z2.y)};
-        else val = {0.5 * (z1.y + z2.y), 0.5 * (z2.x - z1.x)};
+    const cpx<double>* Fs = F + (long long)su * 6 * M * LY;
+    const double sc = scale[u];
+    cpx<double>* reg = sh + grp * fft_region(LY);
+    // output slot of component c6 (-1: not stored)
+    auto oc_of = [&](int c6) { return comps == 6 ? c6 : (c6 < 2 ? c6 : (c6 == 2 ? -1 : c6 - 1)); };
+    auto put = [&](int c6, int kx, int ky, double v) {
+        const int oc = oc_of(c6);
+        if (oc < 0) return;
+        const long long o = row_outer
+            ? (((long long)kx * pair_total + pair0 + u) * comps + oc) * QY + ky
+            : (((long long)u * comps + oc) * QX + kx) * QY + ky;
+        Qout[o] = (R)(v * sc);
+    };
+    auto col = [&](int c6, int kx) { return Fs + ((long long)c6 * M + kx) * LY; };
+    if (kxc > 0) {
+        // (c1, c2), the part each contributes (0: real, 1: imaginary), y parity
+        const int c1 = k == 0 ? 0 : (k == 1 ? 2 : 3), c2 = k == 0 ? 1 : (k == 1 ? 4 : 5);
+        const int p1 = k == 2 ? 1 : 0, p2 = k == 1 ? 1 : 0;
+        const double* a = reinterpret_cast<const double*>(col(c1, kxc)) + p1;
+        const double* b = reinterpret_cast<const double*>(col(c2, kxc)) + p2;
+        wave_fft<double, LY, false>(
+            reg, g, twy, 1, [&](int pos) -> cpx<double> { return {a[2 * pos], b[2 * pos]}; },
+            [&](int pos, cpx<double> z) {
+                if (pos > LY / 2) return;
+                if (k < 2) {
+                    put(c1, kxc, pos, z.x);
+                    put(c2, kxc, pos, z.y);
+                } else {
+                    // xy = -Re(i A') ... = -A' = -Im Z; yz = B' = -Re Z
+                    put(3, kxc, pos, -z.y);
+                    put(5, kxc, pos, -z.x);
+                }
+            });
     } else {
-        val = Fs[(long long)kx * Ly + ky];
+        // packed column: x-even components one by one; task 0 takes xx and
+        // yy, task 1 zz (and the zero xz), task 2 yz (and the zero xy)
+        for (int e = 0; e < (k == 0 ? 2 : 1); ++e) {
+            const int c6 = k == 0 ? e : (k == 1 ? 2 : 5);
+            const bool yodd = (c6 == 5);
+            if (!(comps == 5 && c6 == 2)) {
+                const cpx<double>* z0 = col(c6, 0);
+                wave_fft<double, LY, false>(
+                    reg, g, twy, 1, [&](int pos) -> cpx<double> { return z0[pos]; },
+                    [&](int pos, cpx<double> z) {
+                        if (pos > LY / 2) return;
+                        put(c6, 0, pos, yodd ? z.y : z.x);
+                        put(c6, M, pos, yodd ? -z.x : z.y);
+                    });
+            }
+            if (e == 0 && k > 0) {
+                const int cz = k == 1 ? 4 : 3;  // x-odd: zero on the rows kx = 0 and Lx/2
+                for (int pos = g; pos <= LY / 2; pos += S::GT) {
+                    put(cz, 0, pos, 0.0);
+                    put(cz, M, pos, 0.0);
+                }
+            }
+            wave_sync();
+        }
     }
-    const bool imag = (c6 == 4 || c6 == 5);
-    const long long o = row_outer
-        ? (((long long)kx * pair_total + pair0 + u) * comps + c) * QY + ky
-        : idx;
-    Qout[o] = (R)((imag ? val.y : val.x) * scale[u]);
 }
 
 }  // namespace hfd
