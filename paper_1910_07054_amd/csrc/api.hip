@@ -178,8 +178,8 @@ struct hfd_plan_s {
     std::vector<double> zeta_host;
     std::vector<int> itab_host;
     bool d_valid = false;       // D holds the current geometry (stored mode)
-    double* dW = nullptr;       // FP64 scratch for the derivative transform
-    void* dF = nullptr;
+    double* dW = nullptr;       // FP64 quadrants of the derivative lattice [chunk][6][ny][nx]
+    void* dF = nullptr;         // their x-pass spectra [chunk][6][Lx/2 + 1][ny]
     double* dscale = nullptr;   // -1/(Lx Ly) per zeta of a chunk
     int dchunk = 0;
     double* partial = nullptr;  // reduction partials [batch_max][ntiles][2 nz]
@@ -203,8 +203,8 @@ struct hfd_plan_s {
     // field and vjp calls are refused until a later set succeeds
     bool ready = true;
     // tensor-setup scratch, allocated once with the plan (set_thickness reuses it)
-    double* sW = nullptr;       // real-space FP64 tables [chunk][6][Ly][Lx]
-    void* sF = nullptr;         // their spectra
+    double* sW = nullptr;       // real-space FP64 quadrants [chunk][6][ny][nx]
+    void* sF = nullptr;         // their x-pass spectra [chunk][6][Lx/2 + 1][ny]
     void* spg = nullptr;        // pair geometries
     double* sscale = nullptr;   // per pair scale
     double* sQ2 = nullptr;      // equidistant plans: per-offset spectra
@@ -369,18 +369,23 @@ hfd_status upload_twiddles(hfd_plan p, hipStream_t s)
     return HFD_OK;
 }
 
-// Tensor-setup scratch, allocated once per plan: real-space tables and their
-// spectra for a chunk of pair geometries (256 MB each at most), the pair list
-// and scales, and for equidistant plans the per-offset spectra.
+// Bytes per pair (or offset) of the FP64 quadrant tables [6][ny][nx] and of
+// their x-pass spectra [6][Lx/2 + 1][ny] (reals).
+static long long quadrant_bytes(hfd_plan p) { return 6LL * p->nx * p->ny * 8; }
+static long long xspectra_bytes(hfd_plan p) { return 6LL * (p->M + 1) * p->ny * 8; }
+
+// Tensor-setup scratch, allocated once per plan: quadrant tables and their
+// x-pass spectra for a chunk of pair geometries (256 MB each at most), the
+// pair list and scales, and for equidistant plans the per-offset spectra.
 hfd_status alloc_setup_scratch(hfd_plan p)
 {
-    const long long per_pair = 6LL * p->Lx * p->Ly * 8;  // FP64 real arrays per pair
+    const long long per_pair = std::max(quadrant_bytes(p), xspectra_bytes(p));
     const int ngeo = std::max(p->P, 2 * p->nz - 1);         // distinct geometries per stack, at most
     const long long budget = 256LL << 20;
     p->schunk = (int)std::max(1LL, std::min<long long>(ngeo, budget / per_pair));
     p->spg_cap = ngeo;
-    HFD_TRY(dev_alloc(&p->sW, (size_t)p->schunk * per_pair, "tensor setup (real space)"));
-    HFD_TRY(dev_alloc(&p->sF, (size_t)p->schunk * per_pair, "tensor setup (spectra)"));
+    HFD_TRY(dev_alloc(&p->sW, (size_t)p->schunk * quadrant_bytes(p), "tensor setup (real space)"));
+    HFD_TRY(dev_alloc(&p->sF, (size_t)p->schunk * xspectra_bytes(p), "tensor setup (spectra)"));
     HFD_TRY(dev_alloc(&p->spg, sizeof(PairGeoH) * (size_t)ngeo, "pair table"));
     HFD_TRY(dev_alloc(&p->sscale, sizeof(double) * (size_t)ngeo, "pair scales"));
     const int nchunks = (ngeo + p->schunk - 1) / p->schunk;
@@ -398,19 +403,17 @@ static double max_thickness(const std::vector<PairGeoH>& geos, int first, int co
     return t;
 }
 
-// FP64 x-pass spectra of the zero-padded real-space tensor (6 components
-// each) of the cuboid-pair geometries `geos`, in chunks of the plan's setup
-// scratch; after each chunk pack(first, count, F) enqueues the y transforms
-// and packing (launch_ytab) of spectra F[count][6][M][Ly] (complex,
-// interleaved re/im doubles).  Synchronizes the stream at the end.
+// FP64 x-pass spectra of the real-space tensor quadrants (6 components each)
+// of the cuboid-pair geometries `geos`, in chunks of the plan's setup scratch;
+// after each chunk pack(first, count, F) enqueues the y transforms and packing
+// (launch_ytab) of spectra F[count][6][M + 1][ny] (reals, launch_xtab).
+// Synchronizes the stream at the end.
 
 template <class Pack>
 hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStream_t s, Pack pack)
 {
     const int n = (int)geos.size();
     if (n > p->spg_cap) return fail(HFD_EINVAL, "internal: more pair geometries than the setup scratch holds");
-    const long long plane = (long long)p->Lx * p->Ly;
-    const long long per_pair = 6 * plane * 8;
     const int CP = p->schunk;
     double* W = p->sW;
     void* F = p->sF;
@@ -418,13 +421,10 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
     hipError_t e = hipMemcpyAsync(pg, geos.data(), sizeof(PairGeoH) * n, hipMemcpyHostToDevice, s);
     for (int u0 = 0; u0 < n && e == hipSuccess; u0 += CP) {
         const int np = std::min(CP, n - u0);
-        // the lattice kernels write every entry of the quadrant and its images
-        e = launch_zero_gaps(W, (long long)np * 6, p->nx, p->ny, p->Lx, p->Ly, s);
-        if (e == hipSuccess)
-            e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy,
-                                   max_thickness(geos, u0, np), 0, s);
-        if (e == hipSuccess)
-            e = launch_xfwd(true, p->Lx, W, F, p->Lx, p->Ly, plane, p->Lx, np * 6, p->twx64, s);
+        // quadrants; the transforms extend them by parity
+        e = launch_tensor_real(W, pg + u0, np, p->nx, p->ny, p->Lx, p->Ly, p->dx, p->dy,
+                               max_thickness(geos, u0, np), 2, s);
+        if (e == hipSuccess) e = launch_xtab(p->Lx, W, F, p->nx, p->ny, np * 6, p->twx64, s);
         if (e == hipSuccess) e = pack(u0, np, (const double*)F);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -477,8 +477,8 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
         }
         st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
             (void)np;
-            return launch_ytab(p->fp64, F, qdst, scale, p->P, 5, p->M, p->Ly, p->QX, p->QY, 0, p->P, 1,
-                               p->twy64, s, p->spmap + (size_t)(u0 / CP) * p->P);
+            return launch_ytab(p->fp64, F, qdst, scale, p->P, 5, p->M, p->ny, p->Ly, p->QX, p->QY, 0,
+                               p->P, 1, p->twy64, s, p->spmap + (size_t)(u0 / CP) * p->P);
         });
     }
     (void)hipStreamSynchronize(s);
@@ -525,8 +525,8 @@ hfd_status build_tensor3d(hfd_plan p, hipStream_t s)
         st = fail(HFD_EHIP, "tensor setup: scale upload failed");
     if (st == HFD_OK)
         st = tensor_spectra(p, geos, s, [&](int u0, int np, const double* F) -> hipError_t {
-            return launch_ytab(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->Ly, p->QX,
-                               p->QY, 0, np, 0, p->twy64, s);
+            return launch_ytab(true, F, Q2 + (size_t)u0 * per, scale + u0, np, 6, p->M, p->ny, p->Ly,
+                               p->QX, p->QY, 0, np, 0, p->twy64, s);
         });
     if (st == HFD_OK) {
         hipError_t e = launch_zdft3(p->fp64, Q2, p->Q, p->nz, p->Lz, p->QX, p->QY, s);
@@ -741,7 +741,7 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     if (!p->itab) HFD_TRY(dev_alloc(&p->itab, sizeof(int) * itab.size(), "interface table"));
     p->itab_stride = itab_layout(p->nz).stride;
     const long long plane = (long long)p->Lx * p->Ly;
-    const long long per_z = 6 * plane * 8;
+    const long long per_z = std::max(quadrant_bytes(p), xspectra_bytes(p));
     const int chunk = (int)std::max(1LL, std::min<long long>(nmax, (256LL << 20) / per_z));
     if (chunk > p->dchunk) {
         double *nW = nullptr, *nsc = nullptr;
@@ -787,21 +787,19 @@ hfd_status setup_derivatives(hfd_plan p, hipStream_t s)
     return HFD_OK;
 }
 
-// D(|zeta|) of offset table k (the shared table when stored, else stack k)
-// into p->D: FP64 lattice of the lateral-stencilled z-derivative, FP64 2D FFT,
-// packed to plan precision.
+// D(|zeta|) of offset table k (the shared table when stored, else group k)
+// into p->D: FP64 quadrant of the lateral-stencilled z-derivative, FP64 2D
+// transforms by parity, packed to plan precision.
 hfd_status compute_derivatives(hfd_plan p, int g, hipStream_t s)
 {
-    const long long plane = (long long)p->Lx * p->Ly;
     const int nzt = p->nzeta[g];
     char* dst = (char*)p->D;
     for (int z0 = 0; z0 < nzt; z0 += p->dchunk) {
         const int nc = std::min(p->dchunk, nzt - z0);
-        HFD_HIP(launch_zero_gaps((double*)p->dW, (long long)nc * 6, p->nx, p->ny, p->Lx, p->Ly, s));
         HFD_HIP(launch_dtensor_real(p->dW, p->zeta_dev + (size_t)g * p->nzeta_max + z0, nc, p->nx,
-                                    p->ny, p->Lx, p->Ly, p->dx, p->dy, s));
-        HFD_HIP(launch_xfwd(true, p->Lx, p->dW, p->dF, p->Lx, p->Ly, plane, p->Lx, nc * 6, p->twx64, s));
-        HFD_HIP(launch_ytab(p->fp64, p->dF, dst, p->dscale, nc, 6, p->M, p->Ly, p->QX, p->QY, z0,
+                                    p->ny, p->dx, p->dy, s));
+        HFD_HIP(launch_xtab(p->Lx, p->dW, p->dF, p->nx, p->ny, nc * 6, p->twx64, s));
+        HFD_HIP(launch_ytab(p->fp64, p->dF, dst, p->dscale, nc, 6, p->M, p->ny, p->Ly, p->QX, p->QY, z0,
                             p->nzeta_max, 1, p->twy64, s));
     }
     return HFD_OK;

@@ -196,6 +196,66 @@ __global__ __launch_bounds__((XPassShape<R, LX, TYO>::NT), (XPassShape<R, LX, TY
 }
 
 // ---------------------------------------------------------------------------
+// x pass of the tensor tables from their quadrants: row y < ny of array sig
+// holds W(p, y), p < nx, of component sig % 6 (order xx yy zz xy xz yz); the
+// full periodic row of length LX is W(p) at p and sx W(p) at LX - p (sx = -1
+// for the x-odd components xy and xz), zero between.  Its transform is real
+// for an x-even row and imaginary for an x-odd one; that part is stored
+// transposed, out[sig][kx][y] for kx in [0, LX/2] (columns of ny reals; the
+// rows kx = 0 and LX/2 of x-odd components are exactly zero).
+// ---------------------------------------------------------------------------
+template <int LX, int TYO = 0>
+__global__ __launch_bounds__((XPassShape<double, LX, TYO>::NT), (XPassShape<double, LX, TYO>::WPE)) void k_xtab(
+    const double* __restrict__ in, double* __restrict__ out, int nx, int ny, int nrows,
+    const cpx<double>* __restrict__ twx)
+{
+    using R = double;
+    using S = XPassShape<R, LX, TYO>;
+    constexpr int M = S::M, GT = S::GT, NG = S::NG, TY = S::TY, RS = S::RS, NT = S::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* sh = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int r0 = blockIdx.x * TY;
+    const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
+    Twiddles<R, M> tw;
+    tw.load(g, twx, 2);
+    RealSplit<R, LX> split;
+    split.load(g, twx);
+    for (int r = grp; r < TY; r += NG) {
+        const int fr = r0 + r;
+        if (fr >= nrows) break;
+        const int sig = fr / ny, y = fr - sig * ny;
+        const int c6 = sig % 6;
+        const R sx = (c6 == 3 || c6 == 4) ? R(-1) : R(1);
+        const R* src = in + ((long long)sig * ny + y) * nx;
+        auto xv = [&](int x) -> R {
+            if (x < nx) return src[x];
+            const int m = LX - x;
+            return m < nx ? sx * src[m] : R(0);
+        };
+        cpx<R>* row = sh + r * RS;
+        wave_fft<R, M, false>(
+            row, g, tw, [&](int pos) -> cpx<R> { return {xv(2 * pos), xv(2 * pos + 1)}; },
+            [&](int pos, cpx<R> v) { row[pos] = v; });
+        wave_sync();
+        split.forward(row, g);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < (M + 1) * TY; idx += NT) {
+        const int r = idx % TY, kx = idx / TY;
+        const int fr = r0 + r;
+        if (fr < nrows) {
+            const int sig = fr / ny, y = fr - sig * ny;
+            const int c6 = sig % 6;
+            const bool xodd = (c6 == 3 || c6 == 4);
+            // column 0 holds X[0] + i X[M] (both real for an x-even row)
+            const cpx<R> z = sh[r * RS + (kx == M ? 0 : kx)];
+            const R v = xodd ? (kx == 0 || kx == M ? R(0) : z.y) : (kx == M ? z.y : z.x);
+            out[((long long)sig * (M + 1) + kx) * ny + y] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x pass, inverse: packed half spectrum (transposed) -> nx reals per row.
 // Unnormalized; the 1/(Lx Ly) is folded into the tensor.  HALF: nx <= LX/2,
 // only the first half of the transform is kept.

@@ -25,6 +25,12 @@ hipError_t ensure_lds_limit(const void* kernel, int bytes);
 // rows; ty = rows per block (0: the default tile; else one of 4, 8, 16, 24,
 // 32 where x_tile_supported, for rows of nx <= LX/2 values only)
 bool x_tile_supported(bool fp64, int LX, int ty);
+// x transforms of nsig tensor quadrants in[nsig][ny][nx] (FP64; component
+// sig % 6, extended to length LX by its x parity) -> out[nsig][LX/2 + 1][ny],
+// the real part of each transform (x-even components) or the imaginary part
+// (x-odd ones), which is the non-zero one
+hipError_t launch_xtab(int LX, const double* in, void* out, int nx, int ny, int nsig, const void* twx64,
+                       hipStream_t s);
 hipError_t launch_xfwd(bool fp64, int LX, const void* in, void* out, int nx, int ny,
                        long long in_sig_stride, int in_row_stride, int nsig, const void* twx,
                        hipStream_t s, int ty = 0);
@@ -130,23 +136,25 @@ hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz,
 struct PairGeoH {
     double ti, tj, Z, pad;
 };
-// tmax: the largest thickness among the npairs pair records (bounds the near box)
+// tmax: the largest thickness among the npairs pair records (bounds the near box);
+// mode 1: offset table [pair][6][2ny-1][2nx-1], 2: the quadrant [pair][6][ny][nx]
 hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
                               int Ly, double dx, double dy, double tmax, int mode, hipStream_t s);
 // zero n doubles (a kernel, so that graph captures hold no memset node)
 hipError_t launch_zero64(double* p, long long n, hipStream_t s);
-// zero what k_dtensor_real leaves untouched in nplanes padded Lx x Ly planes
-hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx, int Ly, hipStream_t s);
-hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
-                               int Ly, double dx, double dy, hipStream_t s);
-// y transforms of x-pass tensor spectra F[pair][6][M][Ly] (FP64) and their
+// quadrants W[nzeta][6][ny][nx] of the lateral-stencilled z-derivative tables
+hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, double dx,
+                               double dy, hipStream_t s);
+// y transforms of x-pass tensor spectra F[pair][6][M + 1][ny] (FP64 reals as
+// launch_xtab writes them, columns extended to Ly by each component's y
+// parity) and their
 // packing into the quadrant: comps 5 (field tensor) or 6 (all components);
 // row_outer: [QX][pair_total][comps][QY] at pairs pair0.., else
 // [npairs][comps][QX][QY]; times scale[u].  src (device, optional): for output
 // pair u the index of its spectra in F, or -1 to leave the pair alone
 // (default: u itself).  twy64: the FP64 twiddles of length Ly.
 hipError_t launch_ytab(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
-                       int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
+                       int comps, int M, int ny, int Ly, int QX, int QY, int pair0, int pair_total,
                        int row_outer, const void* twy64, hipStream_t s, const int* src = nullptr);
 
 }  // namespace hfd

@@ -11,7 +11,10 @@ static_assert(sizeof(PairGeo) == sizeof(PairGeoH), "pair record layout");
 hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx, int ny, int Lx,
                               int Ly, double dx, double dy, double tmax, int mode, hipStream_t s)
 {
+    (void)Lx;
+    (void)Ly;
     if (npairs <= 0 || nx <= 0 || ny <= 0) return hipSuccess;
+    if (mode != 1 && mode != 2) return hipErrorInvalidValue;
     // boxes of every entry with rho < 6 and rho < 32: p dx and q dy stay below
     // rho max(dx, dy, t)
     const double dmax = std::max(std::max(dx, dy), tmax);
@@ -24,51 +27,50 @@ hipError_t launch_tensor_real(double* W, const PairGeoH* pg, int npairs, int nx,
     if (tiles * npairs > 0x7fffffffLL || npairs > 65535) return hipErrorInvalidValue;
     const dim3 ngrid((unsigned)((pn + kNTile - 1) / kNTile), (unsigned)((qn + kNTile - 1) / kNTile),
                      (unsigned)npairs);
-    hipLaunchKernelGGL(k_tensor_near, ngrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, Lx, Ly,
-                       dx, dy, mode, pn, qn);
+    hipLaunchKernelGGL(k_tensor_near, ngrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, dx, dy,
+                       mode, pn, qn);
     const dim3 mgrid((unsigned)((pm * qm + epb - 1) / epb), (unsigned)npairs);
-    hipLaunchKernelGGL(k_tensor_mid, mgrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, Lx, Ly,
-                       dx, dy, mode, pm, qm);
+    hipLaunchKernelGGL(k_tensor_mid, mgrid, dim3(256), 0, s, W, (const PairGeo*)pg, nx, ny, dx, dy,
+                       mode, pm, qm);
     hipLaunchKernelGGL(k_tensor_far, dim3((unsigned)(tiles * npairs)), dim3(256), 0, s, W,
-                       (const PairGeo*)pg, npairs, nx, ny, Lx, Ly, dx, dy, mode);
+                       (const PairGeo*)pg, npairs, nx, ny, dx, dy, mode);
     return hipGetLastError();
 }
 
-hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, int Lx,
-                               int Ly, double dx, double dy, hipStream_t s)
+hipError_t launch_dtensor_real(double* W, const double* zeta, int nzeta, int nx, int ny, double dx,
+                               double dy, hipStream_t s)
 {
     if (nzeta <= 0) return hipSuccess;
     if (nzeta > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((nx + kDTile - 1) / kDTile), (unsigned)((ny + kDTile - 1) / kDTile),
                     (unsigned)nzeta);
-    hipLaunchKernelGGL(k_dtensor_real, grid, dim3(kDTile * kDTile), 0, s, W, zeta, nx, ny, Lx, Ly,
-                       dx, dy);
+    hipLaunchKernelGGL(k_dtensor_real, grid, dim3(kDTile * kDTile), 0, s, W, zeta, nx, ny, dx, dy);
     return hipGetLastError();
 }
 
 template <typename R, int LY>
 static hipError_t ytab_t(const void* F, void* Q, const double* scale, int npairs, int comps, int M,
-                         int QX, int QY, int pair0, int pair_total, int row_outer, const int* src,
-                         const void* twy, hipStream_t s)
+                         int ny, int QX, int QY, int pair0, int pair_total, int row_outer,
+                         const int* src, const void* twy, hipStream_t s)
 {
     using S = TabShape<LY>;
-    const long long tasks = (long long)npairs * M * 3;
+    const long long tasks = (long long)npairs * (M + 1) * 3;
     const long long nb = (tasks + S::NG - 1) / S::NG;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ytab<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const cpx<double>*)F,
-                       (R*)Q, scale, npairs, comps, M, QX, QY, pair0, pair_total, row_outer, src,
+    hipLaunchKernelGGL((k_ytab<R, LY>), dim3((unsigned)nb), dim3(S::NT), 0, s, (const double*)F,
+                       (R*)Q, scale, npairs, comps, M, ny, QX, QY, pair0, pair_total, row_outer, src,
                        (const cpx<double>*)twy);
     return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t ytab_r(int Ly, const void* F, void* Q, const double* scale, int npairs, int comps,
-                         int M, int QX, int QY, int pair0, int pair_total, int row_outer,
+                         int M, int ny, int QX, int QY, int pair0, int pair_total, int row_outer,
                          const int* src, const void* twy, hipStream_t s)
 {
     switch (Ly) {
 #define HFD_YTAB(L) \
-    case L: return ytab_t<R, L>(F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total, row_outer, src, twy, s);
+    case L: return ytab_t<R, L>(F, Q, scale, npairs, comps, M, ny, QX, QY, pair0, pair_total, row_outer, src, twy, s);
     HFD_YTAB(8) HFD_YTAB(16) HFD_YTAB(32) HFD_YTAB(64) HFD_YTAB(128) HFD_YTAB(256) HFD_YTAB(512)
     HFD_YTAB(1024) HFD_YTAB(2048) HFD_YTAB(4096)
 #undef HFD_YTAB
@@ -77,51 +79,17 @@ static hipError_t ytab_r(int Ly, const void* F, void* Q, const double* scale, in
 }
 
 hipError_t launch_ytab(bool out_fp64, const void* F, void* Q, const double* scale, int npairs,
-                       int comps, int M, int Ly, int QX, int QY, int pair0, int pair_total,
+                       int comps, int M, int ny, int Ly, int QX, int QY, int pair0, int pair_total,
                        int row_outer, const void* twy64, hipStream_t s, const int* src)
 {
     if (npairs <= 0) return hipSuccess;
-    if ((comps != 5 && comps != 6) || M < 1) return hipErrorInvalidValue;
-    return out_fp64 ? ytab_r<double>(Ly, F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total,
+    if ((comps != 5 && comps != 6) || M < 1 || ny < 1 || 2 * ny > Ly + 1) return hipErrorInvalidValue;
+    return out_fp64 ? ytab_r<double>(Ly, F, Q, scale, npairs, comps, M, ny, QX, QY, pair0, pair_total,
                                      row_outer, src, twy64, s)
-                    : ytab_r<float>(Ly, F, Q, scale, npairs, comps, M, QX, QY, pair0, pair_total,
+                    : ytab_r<float>(Ly, F, Q, scale, npairs, comps, M, ny, QX, QY, pair0, pair_total,
                                     row_outer, src, twy64, s);
 }
 
-// Zero the entries of nplanes Lx x Ly planes that the lattice kernels leave
-// untouched: columns x in [nx, Lx - nx] and rows y in [ny, Ly - ny] (the images
-// of the nx x ny quadrant cover every other entry).
-__global__ __launch_bounds__(256) void k_zero_gaps(double* __restrict__ W, long long nplanes, int nx,
-                                                  int ny, int Lx, int Ly)
-{
-    const int gx = Lx - 2 * nx + 1, gy = Ly - 2 * ny + 1;
-    const long long per = (long long)gx * Ly + (long long)gy * Lx;
-    const long long n = per * nplanes;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const long long pl = i / per, r = i - pl * per;
-        int x, y;
-        if (r < (long long)gx * Ly) {
-            x = nx + (int)(r % gx);
-            y = (int)(r / gx);
-        } else {
-            const long long r2 = r - (long long)gx * Ly;
-            x = (int)(r2 % Lx);
-            y = ny + (int)(r2 / Lx);
-        }
-        W[pl * Lx * Ly + (long long)y * Lx + x] = 0.0;
-    }
-}
-
-hipError_t launch_zero_gaps(double* W, long long nplanes, int nx, int ny, int Lx, int Ly, hipStream_t s)
-{
-    if (nplanes <= 0) return hipSuccess;
-    if (Lx < 2 * nx || Ly < 2 * ny) return hipErrorInvalidValue;
-    const long long per = (long long)(Lx - 2 * nx + 1) * Ly + (long long)(Ly - 2 * ny + 1) * Lx;
-    const long long blocks = std::min<long long>((per * nplanes + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_zero_gaps, dim3((unsigned)blocks), dim3(256), 0, s, W, nplanes, nx, ny, Lx, Ly);
-    return hipGetLastError();
-}
 
 // Zero n doubles with a kernel (used instead of a memset node on paths that a
 // caller may capture in a graph).

@@ -339,34 +339,24 @@ __device__ inline double parity_sign(int c, int sx, int sy)
     }
 }
 
-// Write component c of the quadrant entry (p, q) of pair u with its sign images.
-// mode 0: the zero-padded periodic arrays W[pair][6][Ly][Lx] (W zeroed beforehand);
-// mode 1: the offset table W[pair][6][2ny-1][2nx-1].
+// Write component c of the quadrant entry (p, q) of pair u.
+// mode 1: the offset table W[pair][6][2ny-1][2nx-1], with the sign images;
+// mode 2: the quadrant alone, W[pair][6][ny][nx] (the transforms supply the images).
 __device__ inline void store_component(double* __restrict__ W, int mode, int u, int c, int p, int q,
-                                       double v, int nx, int ny, int Lx, int Ly)
+                                       double v, int nx, int ny)
 {
     if ((p == 0 && (c == 3 || c == 4)) || (q == 0 && (c == 3 || c == 5))) v = 0.0;  // odd axes
-    if (mode == 0) {
-        const long long plane = (long long)Lx * Ly;
-        double* base = W + ((long long)u * 6 + c) * plane;
-        for (int sy = 1; sy >= -1; sy -= 2) {
-            if (sy < 0 && q == 0) continue;
-            const int qq = sy > 0 ? q : Ly - q;
-            for (int sx = 1; sx >= -1; sx -= 2) {
-                if (sx < 0 && p == 0) continue;
-                const int pp = sx > 0 ? p : Lx - p;
-                base[(long long)qq * Lx + pp] = parity_sign(c, sx, sy) * v;
-            }
-        }
-    } else {
-        const int Wo = 2 * nx - 1, Ho = 2 * ny - 1;
-        double* base = W + ((long long)u * 6 + c) * Wo * Ho;
-        for (int sy = 1; sy >= -1; sy -= 2) {
-            if (sy < 0 && q == 0) continue;
-            for (int sx = 1; sx >= -1; sx -= 2) {
-                if (sx < 0 && p == 0) continue;
-                base[(long long)(sy * q + ny - 1) * Wo + (sx * p + nx - 1)] = parity_sign(c, sx, sy) * v;
-            }
+    if (mode == 2) {
+        W[(((long long)u * 6 + c) * ny + q) * nx + p] = v;
+        return;
+    }
+    const int Wo = 2 * nx - 1, Ho = 2 * ny - 1;
+    double* base = W + ((long long)u * 6 + c) * Wo * Ho;
+    for (int sy = 1; sy >= -1; sy -= 2) {
+        if (sy < 0 && q == 0) continue;
+        for (int sx = 1; sx >= -1; sx -= 2) {
+            if (sx < 0 && p == 0) continue;
+            base[(long long)(sy * q + ny - 1) * Wo + (sx * p + nx - 1)] = parity_sign(c, sx, sy) * v;
         }
     }
 }
@@ -386,7 +376,7 @@ __device__ inline void store_component(double* __restrict__ W, int mode, int u, 
 constexpr int kNTile = 4;
 __global__ __launch_bounds__(256) void k_tensor_near(double* __restrict__ W,
                                                      const PairGeo* __restrict__ pg, int nx, int ny,
-                                                     int Lx, int Ly, double dx, double dy, int mode,
+                                                     double dx, double dy, int mode,
                                                      int pn, int qn)
 {
     constexpr int E = kNTile + 2, EE = E * E;
@@ -419,7 +409,7 @@ __global__ __launch_bounds__(256) void k_tensor_near(double* __restrict__ W,
             acc += w3[a] * w3[b] * s;
         }
     const double pref = -1.0 / (4.0 * M_PI * dx * dy * G.ti);
-    store_component(W, mode, u, c, p, q, pref * acc, nx, ny, Lx, Ly);
+    store_component(W, mode, u, c, p, q, pref * acc, nx, ny);
 }
 
 // Entries with 6 <= rho < 32 (5 and 4 points per piece, up to 15 z points
@@ -429,7 +419,7 @@ __global__ __launch_bounds__(256) void k_tensor_near(double* __restrict__ W,
 constexpr int kMidLanes = 16;
 __global__ __launch_bounds__(256) void k_tensor_mid(double* __restrict__ W,
                                                     const PairGeo* __restrict__ pg, int nx, int ny,
-                                                    int Lx, int Ly, double dx, double dy, int mode,
+                                                    double dx, double dy, int mode,
                                                     int pm, int qm)
 {
     const int l = threadIdx.x % kMidLanes;
@@ -462,7 +452,7 @@ __global__ __launch_bounds__(256) void k_tensor_mid(double* __restrict__ W,
         for (int i = 0; i < 5; ++i) S[i] += __shfl_xor(S[i], off, kMidLanes);
     double N[6];
     gl_finish(S, dx, dy, G.ti, N);
-    if (l < 6) store_component(W, mode, u, l, p, q, N[l], nx, ny, Lx, Ly);
+    if (l < 6) store_component(W, mode, u, l, p, q, N[l], nx, ny);
 }
 
 // Entries with rho >= 32 (3 points per piece below rho = 100, 2 beyond), one
@@ -471,8 +461,8 @@ __global__ __launch_bounds__(256) void k_tensor_mid(double* __restrict__ W,
 // origin outwards, so that the tiles with the most points start first.
 __global__ __launch_bounds__(256) void k_tensor_far(double* __restrict__ W,
                                                     const PairGeo* __restrict__ pg, int npairs,
-                                                    int nx, int ny, int Lx, int Ly, double dx,
-                                                    double dy, int mode)
+                                                    int nx, int ny, double dx, double dy,
+                                                    int mode)
 {
     const int u = (int)(blockIdx.x % (unsigned)npairs), t = (int)(blockIdx.x / (unsigned)npairs);
     const int ntx = (nx + 15) / 16;
@@ -488,12 +478,12 @@ __global__ __launch_bounds__(256) void k_tensor_far(double* __restrict__ W,
     if (rho < 100.0) gl_entry<3>(X, Y, G.Z, dx, dy, G.ti, G.tj, N);
     else gl_entry<2>(X, Y, G.Z, dx, dy, G.ti, G.tj, N);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) store_component(W, mode, u, c, p, q, N[c], nx, ny, Lx, Ly);
+    for (int c = 0; c < 6; ++c) store_component(W, mode, u, c, p, q, N[c], nx, ny);
 }
 
 // Lateral-stencilled z-derivative of Phi at height zeta (one per distinct
 // interface difference):  d(p, q) = -1/(4 pi dx dy) sum_{a,b} s_a s_b
-// dPhi_kl/dz(p dx + a, q dy + b, zeta), written like mode 0 above.
+// dPhi_kl/dz(p dx + a, q dy + b, zeta), written as quadrants W[zeta][6][ny][nx].
 // The stencil points of neighbouring lattice entries are the lattice points
 // themselves, so a block evaluates dPhi/dz once on its tile of 16 x 16
 // entries plus a one-point halo (18 x 18 points, LDS) and applies the 3 x 3
@@ -501,8 +491,8 @@ __global__ __launch_bounds__(256) void k_tensor_far(double* __restrict__ W,
 constexpr int kDTile = 16;
 __global__ __launch_bounds__(kDTile * kDTile) void k_dtensor_real(double* __restrict__ W,
                                                                   const double* __restrict__ zeta,
-                                                                  int nx, int ny, int Lx, int Ly,
-                                                                  double dx, double dy)
+                                                                  int nx, int ny, double dx,
+                                                                  double dy)
 {
     constexpr int E = kDTile + 2;  // tile with halo
     __shared__ double F[6][E][E];
@@ -531,35 +521,24 @@ __global__ __launch_bounds__(kDTile * kDTile) void k_dtensor_real(double* __rest
     }
     if (p == 0) { N[3] = 0.0; N[4] = 0.0; }
     if (q == 0) { N[3] = 0.0; N[5] = 0.0; }
-    const long long plane = (long long)Lx * Ly;
-    double* base = W + (long long)u * 6 * plane;
-    for (int sy = 1; sy >= -1; sy -= 2) {
-        if (sy < 0 && q == 0) continue;
-        const int qq = sy > 0 ? q : Ly - q;
-        for (int sx = 1; sx >= -1; sx -= 2) {
-            if (sx < 0 && p == 0) continue;
-            const int pp = sx > 0 ? p : Lx - p;
-            for (int c = 0; c < 6; ++c)
-                base[c * plane + (long long)qq * Lx + pp] = parity_sign(c, sx, sy) * N[c];
-        }
-    }
+    for (int c = 0; c < 6; ++c) W[(((long long)u * 6 + c) * ny + q) * nx + p] = N[c];
 }
 
 // y transforms of the tensor tables and their packing, in one kernel.
-// Input: the x-pass spectra F[pair][6][M][Ly] (FP64, complex) of arrays with
-// the lateral parity of the tensor: xx, yy, zz even in x and y, xy odd in
-// both, xz odd in x, yz odd in y.  After the x transform a column kx >= 1 of
-// an x-even component is real and one of an x-odd component imaginary; the y
-// transform of a real y-even column is real, of a y-odd one imaginary.  Two
-// components whose column parts share the y parity therefore take one complex
-// transform of length Ly, z = a + i b, whose real and imaginary parts are the
-// two results (y odd: Z = i (A' + i B'), A' = Im Z, B' = -Re Z): the pairs
-// (xx, yy), (zz, xz) and (xy, yz), three transforms per column instead of six.
-// The packed column 0 holds kx = 0 in its real and kx = Lx/2 in its imaginary
-// part; there the x-odd components vanish and each x-even one is its own pair.
-// Output per component, as the quadrant kx in [0, M], ky in [0, Ly/2] of the
-// 2D transform: its real part for xx, yy, zz, xy, its imaginary part for xz,
-// yz (the non-zero one), times scale[pair].
+// Input: the x-pass spectra of the ny quadrant rows, F[pair][6][M + 1][ny]
+// (FP64): for each component the non-zero part of its x transform, real for
+// the x-even components (xx, yy, zz, yz) and imaginary for the x-odd ones
+// (xy, xz).  A column is extended to length Ly by its y parity: v(y) for
+// y < ny, sy v(Ly - y) for Ly - y < ny, zero between (sy = -1 for the y-odd
+// xy and yz).  The y transform of a real y-even column is real, of a y-odd
+// one imaginary, so two columns of the same y parity take one complex
+// transform z = a + i b whose real and imaginary parts are the two results
+// (y odd: Z = i (A' + i B'), A' = Im Z, B' = -Re Z): the pairs (xx, yy),
+// (zz, xz) and (xy, yz), three transforms per column instead of six.
+// Output per component, the quadrant kx in [0, M], ky in [0, Ly/2] of the 2D
+// transform: its real part for xx, yy, zz, xy, its imaginary part for xz, yz
+// (the non-zero one), times scale[pair].  With F = i f for an x-odd column:
+// xy = Re(i i A') = -A', xz = Im(i A) = A; yz = Im(i A') = A'.
 // comps: 5 (xx, yy, xy, xz, yz; zz follows from the trace) or 6 (all, in the
 // order xx yy zz xy xz yz); row_outer: output [kx][pair_total][comps][ky] with
 // this call's pairs at pair0, else [pair][comps][kx][ky].  src (optional): the
@@ -576,79 +555,53 @@ struct TabShape {
 
 template <typename R, int LY>
 __global__ __launch_bounds__((TabShape<LY>::NT)) void k_ytab(
-    const cpx<double>* __restrict__ F, R* __restrict__ Qout, const double* __restrict__ scale,
-    int npairs, int comps, int M, int QX, int QY, int pair0, int pair_total, int row_outer,
+    const double* __restrict__ F, R* __restrict__ Qout, const double* __restrict__ scale,
+    int npairs, int comps, int M, int ny, int QX, int QY, int pair0, int pair_total, int row_outer,
     const int* __restrict__ src, const cpx<double>* __restrict__ twy)
 {
     using S = TabShape<LY>;
     __shared__ cpx<double> sh[S::NG * fft_region(LY)];
     const int grp = threadIdx.x / S::GT, g = threadIdx.x % S::GT;
+    const int ncol = M + 1;
     const long long task = (long long)blockIdx.x * S::NG + grp;
-    if (task >= (long long)npairs * M * 3) return;
+    if (task >= (long long)npairs * ncol * 3) return;
     const int k = (int)(task % 3);
-    const int kxc = (int)((task / 3) % M);
-    const int u = (int)(task / (3LL * M));
+    const int kx = (int)((task / 3) % ncol);
+    const int u = (int)(task / (3LL * ncol));
     const int su = src ? src[u] : u;
     if (su < 0) return;
-    const cpx<double>* Fs = F + (long long)su * 6 * M * LY;
     const double sc = scale[u];
-    cpx<double>* reg = sh + grp * fft_region(LY);
-    // output slot of component c6 (-1: not stored)
-    auto oc_of = [&](int c6) { return comps == 6 ? c6 : (c6 < 2 ? c6 : (c6 == 2 ? -1 : c6 - 1)); };
-    auto put = [&](int c6, int kx, int ky, double v) {
-        const int oc = oc_of(c6);
+    // the pair of columns: (xx, yy), (zz, xz), (xy, yz); the third is y-odd
+    const int c1 = k == 0 ? 0 : (k == 1 ? 2 : 3), c2 = k == 0 ? 1 : (k == 1 ? 4 : 5);
+    const double sy = k == 2 ? -1.0 : 1.0;
+    const double* a = F + (((long long)su * 6 + c1) * ncol + kx) * ny;
+    const double* b = F + (((long long)su * 6 + c2) * ncol + kx) * ny;
+    auto put = [&](int c6, int ky, double v) {
+        const int oc = comps == 6 ? c6 : (c6 < 2 ? c6 : (c6 == 2 ? -1 : c6 - 1));
         if (oc < 0) return;
         const long long o = row_outer
             ? (((long long)kx * pair_total + pair0 + u) * comps + oc) * QY + ky
             : (((long long)u * comps + oc) * QX + kx) * QY + ky;
         Qout[o] = (R)(v * sc);
     };
-    auto col = [&](int c6, int kx) { return Fs + ((long long)c6 * M + kx) * LY; };
-    if (kxc > 0) {
-        // (c1, c2), the part each contributes (0: real, 1: imaginary), y parity
-        const int c1 = k == 0 ? 0 : (k == 1 ? 2 : 3), c2 = k == 0 ? 1 : (k == 1 ? 4 : 5);
-        const int p1 = k == 2 ? 1 : 0, p2 = k == 1 ? 1 : 0;
-        const double* a = reinterpret_cast<const double*>(col(c1, kxc)) + p1;
-        const double* b = reinterpret_cast<const double*>(col(c2, kxc)) + p2;
-        wave_fft<double, LY, false>(
-            reg, g, twy, 1, [&](int pos) -> cpx<double> { return {a[2 * pos], b[2 * pos]}; },
-            [&](int pos, cpx<double> z) {
-                if (pos > LY / 2) return;
-                if (k < 2) {
-                    put(c1, kxc, pos, z.x);
-                    put(c2, kxc, pos, z.y);
-                } else {
-                    // xy = -Re(i A') ... = -A' = -Im Z; yz = B' = -Re Z
-                    put(3, kxc, pos, -z.y);
-                    put(5, kxc, pos, -z.x);
-                }
-            });
-    } else {
-        // packed column: x-even components one by one; task 0 takes xx and
-        // yy, task 1 zz (and the zero xz), task 2 yz (and the zero xy)
-        for (int e = 0; e < (k == 0 ? 2 : 1); ++e) {
-            const int c6 = k == 0 ? e : (k == 1 ? 2 : 5);
-            const bool yodd = (c6 == 5);
-            if (!(comps == 5 && c6 == 2)) {
-                const cpx<double>* z0 = col(c6, 0);
-                wave_fft<double, LY, false>(
-                    reg, g, twy, 1, [&](int pos) -> cpx<double> { return z0[pos]; },
-                    [&](int pos, cpx<double> z) {
-                        if (pos > LY / 2) return;
-                        put(c6, 0, pos, yodd ? z.y : z.x);
-                        put(c6, M, pos, yodd ? -z.x : z.y);
-                    });
+    wave_fft<double, LY, false>(
+        sh + grp * fft_region(LY), g, twy, 1,
+        [&](int pos) -> cpx<double> {
+            if (pos < ny) return {a[pos], b[pos]};
+            const int m = LY - pos;
+            if (m < ny) return {sy * a[m], sy * b[m]};
+            return {0.0, 0.0};
+        },
+        [&](int pos, cpx<double> z) {
+            if (pos > LY / 2) return;
+            if (k < 2) {
+                put(c1, pos, z.x);
+                put(c2, pos, z.y);
+            } else {
+                put(3, pos, -z.y);
+                put(5, pos, -z.x);
             }
-            if (e == 0 && k > 0) {
-                const int cz = k == 1 ? 4 : 3;  // x-odd: zero on the rows kx = 0 and Lx/2
-                for (int pos = g; pos <= LY / 2; pos += S::GT) {
-                    put(cz, 0, pos, 0.0);
-                    put(cz, M, pos, 0.0);
-                }
-            }
-            wave_sync();
-        }
-    }
+        });
 }
 
 }  // namespace hfd

@@ -104,6 +104,41 @@ hipError_t x_lx(int LX, int ty, const void* in, void* out, int nx, int ny, long 
 
 }  // namespace
 
+template <int LX>
+static hipError_t xtab_t(const double* in, void* out, int nx, int ny, long long nrows, const void* tw,
+                         hipStream_t s)
+{
+    using S = XPassShape<double, LX, 0>;
+    hipError_t e = ensure_lds_limit((const void*)k_xtab<LX, 0>, (int)S::LDS);
+    if (e != hipSuccess) return e;
+    if (nrows > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((nrows + S::TY - 1) / S::TY));
+    hipLaunchKernelGGL((k_xtab<LX, 0>), grid, dim3(S::NT), S::LDS, s, in, (double*)out, nx, ny,
+                       (int)nrows, (const cpx<double>*)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_xtab(int LX, const double* in, void* out, int nx, int ny, int nsig, const void* twx64,
+                       hipStream_t s)
+{
+    if (nsig <= 0 || ny <= 0) return hipSuccess;
+    if (nx < 1 || 2 * nx > LX + 1) return hipErrorInvalidValue;
+    const long long rows = (long long)nsig * ny;
+    switch (LX) {
+    case 8: return xtab_t<8>(in, out, nx, ny, rows, twx64, s);
+    case 16: return xtab_t<16>(in, out, nx, ny, rows, twx64, s);
+    case 32: return xtab_t<32>(in, out, nx, ny, rows, twx64, s);
+    case 64: return xtab_t<64>(in, out, nx, ny, rows, twx64, s);
+    case 128: return xtab_t<128>(in, out, nx, ny, rows, twx64, s);
+    case 256: return xtab_t<256>(in, out, nx, ny, rows, twx64, s);
+    case 512: return xtab_t<512>(in, out, nx, ny, rows, twx64, s);
+    case 1024: return xtab_t<1024>(in, out, nx, ny, rows, twx64, s);
+    case 2048: return xtab_t<2048>(in, out, nx, ny, rows, twx64, s);
+    case 4096: return xtab_t<4096>(in, out, nx, ny, rows, twx64, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 bool x_tile_supported(bool fp64, int LX, int ty)
 {
     if (ty == 0) return true;
