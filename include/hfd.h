@@ -208,7 +208,7 @@ hfd_status hfd_autotune(hfd_plan plan, int batch, void *stream, char *report, in
  * (hfd_autotune): path 0 fused y-pass, 1 five-pass with per-frequency mixing,
  * 2 five-pass with batched FP32 mixing, 3 five-pass with split-BF16 MFMA
  * mixing (plans created with HFD_MIX_SPLIT_BF16), 4 equidistant plans; x_tile
- * = rows per block of the x passes (0 = default tile, or 4, 8, 16, 24, 32
+ * = rows per block of the x passes (0 = default tile, or 4, 8, 12, 16, 24, 32
  * where the block fits).  path < 0 drops the pinned choice.  Host only;
  * HFD_EINVAL for a configuration the plan cannot run. */
 hfd_status hfd_set_path(hfd_plan plan, int batch, int path, int x_tile);

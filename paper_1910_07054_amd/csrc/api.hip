@@ -1336,7 +1336,7 @@ hfd_status hfd_autotune(hfd_plan p, int batch, void* stream, char* report, int r
         // stage 2: rows per block of the x passes for the chosen path
         if (st == HFD_OK) {
             rep += " | x tile:";
-            for (int ty : {0, 4, 8, 16, 24, 32}) {
+            for (int ty : {0, 4, 8, 12, 16, 24, 32}) {
                 if (!x_tile_supported(p->fp64, p->Lx, ty) || ty == xdef) continue;
                 double per = 0;
                 st = time_cfg(best, ty, batch, per);

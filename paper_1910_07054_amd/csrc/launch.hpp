@@ -22,7 +22,7 @@ constexpr int kMaxL = 4096;
 hipError_t ensure_lds_limit(const void* kernel, int bytes);
 
 // x pass, forward / inverse (R = float if !fp64 else double) over nsig * ny
-// rows; ty = rows per block (0: the default tile; else one of 4, 8, 16, 24,
+// rows; ty = rows per block (0: the default tile; else one of 4, 8, 12, 16, 24,
 // 32 where x_tile_supported, for rows of nx <= LX/2 values only)
 bool x_tile_supported(bool fp64, int LX, int ty);
 // x transforms of nsig tensor quadrants in[nsig][ny][nx] (FP64; component

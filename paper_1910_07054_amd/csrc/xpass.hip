@@ -76,6 +76,7 @@ hipError_t x_ty(int ty, const void* in, void* out, int nx, int ny, long long ss,
     case 0: return x_one<FWD, R, LX, 0>(in, out, nx, ny, ss, rs, nsig, tw, s);
     case 4: return x_one<FWD, R, LX, 4>(in, out, nx, ny, ss, rs, nsig, tw, s);
     case 8: return x_one<FWD, R, LX, 8>(in, out, nx, ny, ss, rs, nsig, tw, s);
+    case 12: return x_one<FWD, R, LX, 12>(in, out, nx, ny, ss, rs, nsig, tw, s);
     case 16: return x_one<FWD, R, LX, 16>(in, out, nx, ny, ss, rs, nsig, tw, s);
     case 24: return x_one<FWD, R, LX, 24>(in, out, nx, ny, ss, rs, nsig, tw, s);
     case 32: return x_one<FWD, R, LX, 32>(in, out, nx, ny, ss, rs, nsig, tw, s);
@@ -142,7 +143,7 @@ hipError_t launch_xtab(int LX, const double* in, void* out, int nx, int ny, int 
 bool x_tile_supported(bool fp64, int LX, int ty)
 {
     if (ty == 0) return true;
-    if (ty != 4 && ty != 8 && ty != 16 && ty != 24 && ty != 32) return false;
+    if (ty != 4 && ty != 8 && ty != 12 && ty != 16 && ty != 24 && ty != 32) return false;
     const int M = LX / 2;
     const int V = fft_vals(M), GT = M / V;
     const size_t lds = (fp64 ? 16 : 8) * (size_t)ty * (size_t)(fft_region(M) | 1);

@@ -290,7 +290,7 @@ def test_every_x_tile_matches_oracle(nx, ny, nz, fp64):
             for b in range(2)]
     tried = 0
     for path in (0, 1):
-        for ty in (0, 4, 8, 16, 24, 32):
+        for ty in (0, 4, 8, 12, 16, 24, 32):
             try:
                 plan.set_path(2, path, ty)
             except hfd.HFDError:
