@@ -306,9 +306,12 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
 // ky = t and LY - t (t = ty*32 + s; lane 2s+1 of t = 0 takes ky = LY/2), which
 // share every quadrant value of D and Q.  Each lane accumulates its own
 // per-position sums in LDS; the block sums them over the lanes at the end.
-// Blocks of one kx tile and the bpg states that share a geometry are 8 block
-// indices apart, so they run on one XCD and read the geometry's D and Q
-// through its L2.
+// Block order: groups of 8 tiles, within a group every state of the launch,
+// with the 8 tiles on consecutive block indices: the states of one tile are 8
+// indices apart, so they run one after the other on one XCD and read that
+// tile's slice of the offset table D (shared by every stack when stored) and
+// of their geometry's Q through its L2, instead of streaming the whole table
+// once per state.
 // itab per geometry: see itab_layout.  D per geometry: [QX][nzt][6][QY], nzt D slots per row.
 // lp per geometry: 1/t_l, then the trace term of the diagonal blocks.
 // partial[b][tile][2nz]: the block's position gradients.
@@ -319,15 +322,13 @@ __global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
                                               const R* __restrict__ D, int nzt,
                                               const int* __restrict__ itab, int itab_stride,
                                               const R* __restrict__ lp, int bpg,
-                                              int QY, int b0, int ntiles,
+                                              int QY, int b0, int nst, int ntiles,
                                               double* __restrict__ partial)
 {
     const int L = blockIdx.x, r8 = L >> 3;
-    const int ntile8 = (ntiles + 7) >> 3;
-    const int sg = r8 % bpg, rest = r8 / bpg;
-    const int tile = (rest % ntile8) * 8 + (L & 7);
+    const int tile = (r8 / nst) * 8 + (L & 7);
     if (tile >= ntiles) return;
-    const int b = b0 + (rest / ntile8) * bpg + sg;
+    const int b = b0 + r8 % nst;
     const int geom = b / bpg;
     const int half = LY >> 1;
     const int tpk = (half + 31) >> 5;
@@ -418,12 +419,12 @@ hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M
         hipLaunchKernelGGL((k_tgrad<double, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<double>*)Mh, (const cpx<double>*)Gh, nz, M, LY,
                            (const double*)Q, qgs, (const double*)D, nzt, itab, itab_stride,
-                           (const double*)lp, bpg, QY, b0, ntiles, partial);
+                           (const double*)lp, bpg, QY, b0, nb, ntiles, partial);
     else
         hipLaunchKernelGGL((k_tgrad<float, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<float>*)Mh, (const cpx<float>*)Gh, nz, M, LY,
                            (const float*)Q, qgs, (const float*)D, nzt, itab, itab_stride,
-                           (const float*)lp, bpg, QY, b0, ntiles, partial);
+                           (const float*)lp, bpg, QY, b0, nb, ntiles, partial);
     return hipGetLastError();
 }
 
