@@ -55,6 +55,37 @@ def test_every_cell_matches_bruteforce(name, split):
     assert err < 1e-5
 
 
+def test_c3_every_state_matches_its_single_state_call():
+    """Every one of the 64 C3 states, every cell: the batched launch (the
+    autotuned configuration the benchmark times, state-ordered runs) against
+    64 calls of one state each on a plan tuned for one state.  The single-state
+    path is the one checked against the oracle cell by cell (C2, M0) and at
+    sampled cells of four C3 states; this extends that check to the whole
+    batch.  Both are FP32 with the same tensor; each state's arithmetic does not
+    depend on the batch it sits in (measured: bit-identical), and the bound
+    leaves room for a tile shape that changes the order of FP32 sums."""
+    import torch
+    wl = W.c3()
+    B = wl.batch
+    m = torch.from_numpy(wl.m.astype(np.float32)).cuda()
+    pb = plan_for(wl)
+    pb.autotune(B)
+    hb = pb.field(m)
+    p1 = plan_for(wl, batch_max=1)
+    p1.autotune(1)
+    worst = 0.0
+    for b in range(B):
+        h1 = p1.field(m[b:b + 1].contiguous())
+        d = (hb[b] - h1[0]).abs().max().item()
+        scale = h1[0].abs().max().item()
+        worst = max(worst, d / scale)
+    torch.cuda.synchronize()
+    pb.destroy()
+    p1.destroy()
+    print(f"C3: worst state, batched vs single-state, max |dh| / max |h| = {worst:.2e}")
+    assert worst < 2e-6
+
+
 @pytest.mark.parametrize("name,split", [("C2", False), ("M0", False), ("M0", True), ("C3", False),
                                         ("C3", "bf16"), ("C3", "fp32"), ("C4", False), ("C5", False)])
 def test_sampled_cells_match_oracle(name, split):
