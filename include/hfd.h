@@ -236,10 +236,13 @@ typedef struct {
     int fused;              /* 1: three-pass path (fused y-pass), 0: five passes   */
     int fp64;               /* 1 if the field path runs in FP64                    */
     int mix_bf16;           /* 1 if the z-mixing runs on split-BF16 MFMA           */
-    long long tensor_bytes; /* bytes of the stored Fourier tensor (all stacks)     */
+    long long tensor_bytes; /* bytes allocated for the Fourier tensor (all stacks) */
     long long work_bytes;   /* bytes of the field workspace                        */
     int equidistant;        /* 1 for an HFD_EQUIDISTANT plan                       */
     int Lz;                 /* padded length along z (equidistant plans), else 0   */
+    int tensor_slots;       /* distinct pair tensors stored (pairs of equal
+                               thicknesses and offset share one, also across
+                               stacks); 0 for equidistant plans                   */
 } hfd_info;
 hfd_status hfd_get_info(hfd_plan plan, hfd_info *info);
 

@@ -156,8 +156,19 @@ struct hfd_plan_s {
     size_t rsz = 4, csz = 8;
     std::vector<double> thick, zbot;  // [G][nz]
     // device
-    void* Q = nullptr;          // [G][P][5][QX][QY]
-    long long q_geom_stride = 0;
+    // Fourier tensor.  Non-equidistant plans: one table of pair slots
+    // [QX][nslot][5][QY] (qcs = nslot * 5 * QY elements per kx row, rows in
+    // the order kx = 0, M, 1, .., M - 1, see tab_row); pair u of
+    // stack g reads slot qslot[g * P + u], and stacks whose pairs have the same
+    // geometry (thicknesses and offset) share the slot.  nslot = G * P, so any
+    // geometry fits without reallocation.  Equidistant plans: the 3-D tensor.
+    void* Q = nullptr;
+    long long q_geom_stride = 0;  // elements of one stack's tensor ([QX][P][5][QY], export)
+    long long qcs = 0;
+    int nslot = 0;
+    int nslot_used = 0;           // distinct pair geometries of the current thicknesses
+    int* qslot = nullptr;         // device [G][P]
+    std::vector<int> qslot_host;
     void* lp = nullptr;         // [G][2][nz]
     void* twx = nullptr;        // plan precision, length Lx
     void* twy = nullptr;        // plan precision, length Ly
@@ -208,7 +219,6 @@ struct hfd_plan_s {
     void* spg = nullptr;        // pair geometries
     double* sscale = nullptr;   // per pair scale
     double* sQ2 = nullptr;      // equidistant plans: per-offset spectra
-    int* spmap = nullptr;       // per setup chunk and pair: the pair's spectra in the chunk, or -1
     int schunk = 0, spg_cap = 0;
 };
 
@@ -301,7 +311,7 @@ void free_plan_memory(hfd_plan p)
     if (p->twy == p->twy64) p->twy = nullptr;
     void* bufs[] = {p->Q, p->lp, p->twx, p->twy, p->twx64, p->twy64, p->X1, p->Mh, p->Hh,
                     p->D, p->itab, p->zeta_dev, p->partial, p->dW, p->dF, p->dscale, p->Bc, p->twz,
-                    p->sW, p->sF, p->spg, p->sscale, p->sQ2, p->spmap};
+                    p->sW, p->sF, p->spg, p->sscale, p->sQ2, p->qslot};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     p->dW = nullptr;
@@ -319,7 +329,7 @@ void free_plan_memory(hfd_plan p)
     p->spg = nullptr;
     p->sscale = nullptr;
     p->sQ2 = nullptr;
-    p->spmap = nullptr;
+    p->qslot = nullptr;
 }
 
 // twiddle table exp(-2 pi i m / L), m in [0, L), in FP64 (exact octant reduction)
@@ -380,7 +390,8 @@ static long long xspectra_bytes(hfd_plan p) { return 6LL * (p->M + 1) * p->ny * 
 hfd_status alloc_setup_scratch(hfd_plan p)
 {
     const long long per_pair = std::max(quadrant_bytes(p), xspectra_bytes(p));
-    const int ngeo = std::max(p->P, 2 * p->nz - 1);         // distinct geometries per stack, at most
+    // distinct geometries of all stacks, at most
+    const int ngeo = (int)std::max((long long)p->G * p->P, 2LL * p->nz - 1);
     const long long budget = 256LL << 20;
     p->schunk = (int)std::max(1LL, std::min<long long>(ngeo, budget / per_pair));
     p->spg_cap = ngeo;
@@ -388,8 +399,6 @@ hfd_status alloc_setup_scratch(hfd_plan p)
     HFD_TRY(dev_alloc(&p->sF, (size_t)p->schunk * xspectra_bytes(p), "tensor setup (spectra)"));
     HFD_TRY(dev_alloc(&p->spg, sizeof(PairGeoH) * (size_t)ngeo, "pair table"));
     HFD_TRY(dev_alloc(&p->sscale, sizeof(double) * (size_t)ngeo, "pair scales"));
-    const int nchunks = (ngeo + p->schunk - 1) / p->schunk;
-    HFD_TRY(dev_alloc(&p->spmap, sizeof(int) * (size_t)p->P * nchunks, "pair map"));
     if (p->eq3d)
         HFD_TRY(dev_alloc(&p->sQ2, sizeof(double) * 6 * (size_t)p->QX * p->QY * (2 * p->nz - 1),
                           "per-offset spectra"));
@@ -433,21 +442,22 @@ hfd_status tensor_spectra(hfd_plan p, const std::vector<PairGeoH>& geos, hipStre
 }
 
 // Build the Fourier tensor of every stack (FP64 setup, stored in plan precision).
-// Pairs with the same geometry (thicknesses and offset; e.g. every pair at
-// the same layer distance of an equal-thickness stack) are computed once.
+// Every distinct pair geometry (thicknesses and offset) of all stacks is
+// computed once and stored in one slot: pairs at the same layer distance of an
+// equal-thickness stack, and the pairs that thickness candidates of one stack
+// have in common, share it.
 hfd_status build_tensor(hfd_plan p, hipStream_t s)
 {
     const long long plane = (long long)p->Lx * p->Ly;
     double* scale = p->sscale;
     hfd_status st = HFD_OK;
     std::vector<PairGeoH> ug;
-    std::vector<int> uid((size_t)p->P), pmap;
-    std::vector<double> hs((size_t)p->P);
-    for (int g = 0; g < p->G && st == HFD_OK; ++g) {
+    std::vector<double> hs;
+    std::map<std::tuple<double, double, double>, int> seen;
+    p->qslot_host.assign((size_t)p->G * p->P, 0);
+    for (int g = 0; g < p->G; ++g) {
         const double* t = &p->thick[(size_t)g * p->nz];
         const double* z = &p->zbot[(size_t)g * p->nz];
-        ug.clear();
-        std::map<std::tuple<double, double, double>, int> seen;
         int u = 0;
         for (int i = 0; i < p->nz; ++i)
             for (int j = i; j < p->nz; ++j, ++u) {
@@ -456,31 +466,21 @@ hfd_status build_tensor(hfd_plan p, hipStream_t s)
                 if (it == seen.end()) {
                     it = seen.emplace(key, (int)ug.size()).first;
                     ug.push_back({t[i], t[j], z[i] - z[j], 0.0});
+                    hs.push_back(-t[i] / (double)plane);
                 }
-                uid[u] = it->second;
-                hs[u] = -t[i] / (double)plane;
+                p->qslot_host[(size_t)g * p->P + u] = it->second;
             }
-        if (hipMemcpyAsync(scale, hs.data(), sizeof(double) * p->P, hipMemcpyHostToDevice, s) != hipSuccess) {
-            st = fail(HFD_EHIP, "tensor setup: scale upload failed");
-            break;
-        }
-        char* qdst = (char*)p->Q + (size_t)g * p->q_geom_stride * p->rsz;
-        // per setup chunk: which of its spectra each pair takes (pairs with the
-        // same geometry share one), packed by one launch per chunk
-        const int CP = p->schunk, nch = ((int)ug.size() + CP - 1) / CP;
-        pmap.assign((size_t)nch * p->P, -1);
-        for (int pu = 0; pu < p->P; ++pu) pmap[(size_t)(uid[pu] / CP) * p->P + pu] = uid[pu] % CP;
-        if (hipMemcpyAsync(p->spmap, pmap.data(), sizeof(int) * pmap.size(), hipMemcpyHostToDevice, s) !=
-            hipSuccess) {
-            st = fail(HFD_EHIP, "tensor setup: pair map upload failed");
-            break;
-        }
-        st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
-            (void)np;
-            return launch_ytab(p->fp64, F, qdst, scale, p->P, 5, p->M, p->ny, p->Ly, p->QX, p->QY, 0,
-                               p->P, 1, p->twy64, s, p->spmap + (size_t)(u0 / CP) * p->P);
-        });
     }
+    if (hipMemcpyAsync(scale, hs.data(), sizeof(double) * hs.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(p->qslot, p->qslot_host.data(), sizeof(int) * p->qslot_host.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(HFD_EHIP, "tensor setup: scale or slot upload failed");
+    if (st == HFD_OK)
+        st = tensor_spectra(p, ug, s, [&](int u0, int np, const double* F) -> hipError_t {
+            return launch_ytab(p->fp64, F, p->Q, scale + u0, np, 5, p->M, p->ny, p->Ly, p->QX, p->QY, u0,
+                               p->nslot, 1, p->twy64, s);
+        });
+    if (st == HFD_OK) p->nslot_used = (int)ug.size();
     (void)hipStreamSynchronize(s);
     if (st) return st;
     // layer parameters: 1/t and the self-pair trace -t/(Lx Ly)
@@ -904,12 +904,12 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
             const int bpg_c = bpg >= chunk ? chunk : bpg;
             const char* in_c = (const char*)in + (size_t)b0 * state;
             char* out_c = (char*)out + (size_t)b0 * state;
-            const char* q_c = (const char*)p->Q + (size_t)g0 * p->q_geom_stride * p->rsz;
+            const int* qs_c = p->qslot + (size_t)g0 * p->P;
             const char* lp_c = (const char*)p->lp + (size_t)g0 * 2 * p->nz * p->rsz;
             HFD_HIP(launch_xfwd(p->fp64, p->Lx, in_c, x1, p->nx, p->ny, (long long)p->ny * p->nx,
                                 p->nx, chunk * S, p->twx, s, xty));
-            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, chunk, q_c,
-                                 p->q_geom_stride, p->QX, p->QY, lp_c, bpg_c, adjoint, p->twy, s,
+            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, chunk, p->Q, p->qcs, qs_c,
+                                 p->QX, p->QY, lp_c, bpg_c, adjoint, p->twy, s,
                                  gen));
             HFD_HIP(launch_xinv(p->fp64, p->Lx, x1, out_c, p->nx, p->ny, (long long)p->ny * p->nx,
                                 p->nx, chunk * S, p->twx, s, xty));
@@ -930,8 +930,8 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
     mark();
     if (path == 0) {
         if (on())
-            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, batch, p->Q,
-                                 p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s,
+            HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, x1, p->ny, p->M, batch, p->Q, p->qcs,
+                                 p->qslot, p->QX, p->QY, p->lp, bpg, adjoint, p->twy, s,
                                  gen));
         mark();
     } else {
@@ -948,13 +948,13 @@ hfd_status run_field(hfd_plan p, const void* in, void* out, int batch, int adjoi
             } else if (path == 2 || path == 3) {
                 // packed column by the generic kernel, the rest batched
                 HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                           p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1,
+                                           p->qcs, p->qslot, p->QX, p->QY, p->lp, bpg, adjoint, 0, 1,
                                            s));
                 HFD_HIP(launch_mix_batched(path == 3, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                           p->q_geom_stride, p->QY, p->lp, bpg, adjoint, s));
+                                           p->qcs, p->qslot, p->QY, p->lp, bpg, adjoint, s));
             } else {
                 HFD_HIP(launch_mix_generic(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, batch, p->Q,
-                                           p->q_geom_stride, p->QX, p->QY, p->lp, bpg, adjoint, 0,
+                                           p->qcs, p->qslot, p->QX, p->QY, p->lp, bpg, adjoint, 0,
                                            p->M, s));
             }
         }
@@ -1046,6 +1046,17 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
     const long long mh = mul_ll(mul_ll(mul_ll((long long)batch_max, S), p->M), (long long)p->Ly * (long long)p->csz);
     if (q_elems < 0 || x1 < 0 || mh < 0) { delete p; return fail(HFD_ENOMEM, "size overflow"); }
     p->q_geom_stride = q_per_geom;
+    if (!p->eq3d) {
+        p->nslot = n_geom * p->P;
+        p->qcs = (long long)p->nslot * 5 * p->QY;
+        // kernels read the slot table through 32-bit byte offsets from the
+        // start of a kx row (the packed column: of the first two rows)
+        if (2 * p->qcs * (long long)p->rsz >= (1LL << 31)) {
+            delete p;
+            return fail(HFD_ENOTSUP, "one kx row of the tensor table (n_geom * nz (nz + 1) / 2 pairs) exceeds "
+                                     "2 GiB: use fewer stacks per plan");
+        }
+    }
     p->x1_bytes = (size_t)x1;
     p->mh_bytes = (size_t)mh;
 
@@ -1067,6 +1078,10 @@ hfd_status hfd_setup_tensor(hfd_plan* out, int nx, int ny, double dx, double dy,
         if (st) break;
         st = dev_alloc(&p->lp, (size_t)n_geom * 2 * nz * p->rsz, "layer parameters");
         if (st) break;
+        if (!p->eq3d) {
+            st = dev_alloc(&p->qslot, sizeof(int) * (size_t)p->nslot, "tensor slot map");
+            if (st) break;
+        }
         st = dev_alloc(&p->X1, p->x1_bytes, "x-pass workspace");
         if (st) break;
         st = dev_alloc(&p->Mh, p->mh_bytes, "spectrum workspace");
@@ -1202,16 +1217,16 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
         p->d_valid = true;
     }
     if (stored) {
-        HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->q_geom_stride,
-                             p->D, p->nzeta_max, p->itab, p->itab_stride, p->lp, bpg, p->QX, p->QY,
-                             p->partial, s));
+        HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, 0, batch, p->Q, p->qcs,
+                             p->qslot, p->D, p->nzeta_max, p->itab, p->itab_stride, p->lp, bpg, p->QX,
+                             p->QY, p->partial, s));
     } else {
         // recompute the derivative tensor of one group of stacks at a time
         for (size_t k = 0; k + 1 < p->dgroup.size(); ++k) {
             const int g0 = p->dgroup[k], g1 = p->dgroup[k + 1];
             HFD_TRY(compute_derivatives(p, (int)k, s));
             HFD_HIP(launch_tgrad(p->fp64, p->Mh, p->Hh, p->nz, p->M, p->Ly, g0 * bpg, (g1 - g0) * bpg,
-                                 p->Q, p->q_geom_stride, p->D, p->nzeta_max, p->itab,
+                                 p->Q, p->qcs, p->qslot, p->D, p->nzeta_max, p->itab,
                                  p->itab_stride, p->lp, bpg, p->QX, p->QY, p->partial, s));
         }
     }
@@ -1440,6 +1455,7 @@ hfd_status hfd_get_info(hfd_plan p, hfd_info* info)
     if (p->eq3d) info->work_bytes += 2LL * p->batch_max * 3 * p->nz * p->Ly * (long long)p->csz;
     info->equidistant = p->eq3d;
     info->Lz = p->Lz;
+    info->tensor_slots = p->eq3d ? 0 : p->nslot_used;
     return HFD_OK;
 }
 
@@ -1452,8 +1468,23 @@ hfd_status hfd_export_fourier_tensor(hfd_plan p, int geom, void* dst, long long 
     DeviceGuard dg;
     HFD_HIP(dg.set(p->dev));
     HFD_HIP(hipDeviceSynchronize());
-    HFD_HIP(hipMemcpy(dst, (char*)p->Q + (size_t)geom * p->q_geom_stride * p->rsz, (size_t)bytes,
-                      hipMemcpyDeviceToHost));
+    if (p->eq3d) {
+        HFD_HIP(hipMemcpy(dst, (char*)p->Q + (size_t)geom * p->q_geom_stride * p->rsz, (size_t)bytes,
+                          hipMemcpyDeviceToHost));
+        return HFD_OK;
+    }
+    // gather the stack's pairs from their slots: per pair the table rows kx = 0
+    // and M (stored first) and the block of rows 1 .. M - 1
+    const size_t w = (size_t)5 * p->QY * p->rsz, drow = (size_t)p->P * w, srow = (size_t)p->qcs * p->rsz;
+    for (int u = 0; u < p->P; ++u) {
+        const char* src = (const char*)p->Q + (size_t)p->qslot_host[(size_t)geom * p->P + u] * w;
+        char* d = (char*)dst + (size_t)u * w;
+        HFD_HIP(hipMemcpy(d, src, w, hipMemcpyDeviceToHost));
+        HFD_HIP(hipMemcpy(d + (size_t)p->M * drow, src + srow, w, hipMemcpyDeviceToHost));
+        if (p->M > 1)
+            HFD_HIP(hipMemcpy2D(d + drow, drow, src + 2 * srow, srow, w, (size_t)p->M - 1,
+                                hipMemcpyDeviceToHost));
+    }
     return HFD_OK;
 }
 

@@ -355,37 +355,41 @@ __device__ __forceinline__ void block_apply_e(cpx<R>& hx, cpx<R>& hy, cpx<R>& hz
     }
 }
 
-// Tensor values of one target row i (pairs (i, j), j >= i), 5 components each.
+// Tensor values of one target row i (pairs (i, j), j >= i), 5 components each;
+// sl maps the stack's pair u to its slot of the tensor table.
 template <typename R, int NZMAX>
 struct TensorRow {
     R v[NZMAX][5];
     // row i starts at pair index u = i nz - i (i - 1) / 2
     template <int EDGE = 0>
-    __device__ __forceinline__ void load(const UniformBuf<R>& qcol, unsigned kq, int QY, int nz, int i)
+    __device__ __forceinline__ void load(const UniformBuf<R>& qcol, unsigned kq, int QY, int nz, int i,
+                                         const int* __restrict__ sl)
     {
         const int u = i * nz - i * (i - 1) / 2;
 #pragma unroll
         for (int j = 0; j < NZMAX; ++j)
             if (j >= i && j < nz) {
+                const int slot = sl[u + j - i];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     const bool need = EDGE == 0 || c < 2 || c == 4;
-                    v[j][c] = need ? qcol.ld(kq, (unsigned)(((u + j - i) * 5 + c) * QY)) : R(0);
+                    v[j][c] = need ? qcol.ld(kq, (unsigned)((slot * 5 + c) * QY)) : R(0);
                 }
             }
     }
 };
 
 // One frequency point: H_i += S^{ij} M_j and, for i < j, H_j += conj(S^{ij}) M_i.
-// qcol views the tensor from a wave-uniform base; kq is the lane's element
-// offset of its (kx row, quadrant ky); pair u, component c sits at
-// (u * 5 + c) * QY + kq.  sg is the sign of the ky-odd components (xy, yz).
+// qcol views the tensor table from a wave-uniform base (one kx row); kq is the
+// lane's element offset (the quadrant ky, plus the row for the packed column);
+// pair u, component c sits at (sl[u] * 5 + c) * QY + kq.
+// sg is the sign of the ky-odd components (xy, yz).
 // Row i + 1 of the tensor is loaded while row i is applied; `first` holds
 // row 0, loaded by the caller ahead of time.
 template <typename R, int NZMAX, int EDGE = 0, class In>
 __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
-                                     unsigned kq, int QY, R sg, const R* dg,
-                                     const TensorRow<R, NZMAX>& first)
+                                     unsigned kq, int QY, const int* __restrict__ sl, R sg,
+                                     const R* dg, const TensorRow<R, NZMAX>& first)
 {
 #pragma unroll
     for (int k = 0; k < 3 * NZMAX; ++k) H[k] = {R(0), R(0)};
@@ -397,9 +401,9 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
     for (int i = 0; i < NZMAX; ++i) {
         if (i < nz) {
             if constexpr (DB) {
-                if (i + 1 < NZMAX && i + 1 < nz) nxt.template load<EDGE>(qcol, kq, QY, nz, i + 1);
+                if (i + 1 < NZMAX && i + 1 < nz) nxt.template load<EDGE>(qcol, kq, QY, nz, i + 1, sl);
             } else if (i > 0) {
-                cur.template load<EDGE>(qcol, kq, QY, nz, i);
+                cur.template load<EDGE>(qcol, kq, QY, nz, i, sl);
             }
             const cpx<R> ix = in(0, i), iy = in(1, i), iz = in(2, i);
 #pragma unroll
@@ -430,11 +434,12 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
 
 template <typename R, int NZMAX, int EDGE = 0, class In>
 __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<R>& qcol,
-                                     unsigned kq, int QY, R sg, const R* dg)
+                                     unsigned kq, int QY, const int* __restrict__ sl, R sg,
+                                     const R* dg)
 {
     TensorRow<R, NZMAX> first;
-    first.template load<EDGE>(qcol, kq, QY, nz, 0);
-    mix1<R, NZMAX, EDGE>(nz, in, H, qcol, kq, QY, sg, dg, first);
+    first.template load<EDGE>(qcol, kq, QY, nz, 0, sl);
+    mix1<R, NZMAX, EDGE>(nz, in, H, qcol, kq, QY, sl, sg, dg, first);
 }
 
 // The two points of the packed column that are their own mirror (ky = 0 and
@@ -442,8 +447,9 @@ __device__ __forceinline__ void mix1(int nz, In in, cpx<R>* H, const UniformBuf<
 // the kx = M row, at both points.  With LY lanes for LY + 2 mixings they are
 // spread over the lanes of one wave: lane e takes one (point, part, target
 // layer i) and sums over the source layers.  All blocks there are diagonal
-// and real (xy, xz and yz vanish on those rows and columns).  qb0 views the
-// rows kx = 0 .. M of the tensor; lpg holds 1/t and the trace terms.  The
+// and real (xy, xz and yz vanish on those rows and columns).  Q is the tensor
+// table, whose rows kx = 0 and kx = M come first (Q and Q + qcs), sl the
+// stack's slot map; lpg holds 1/t and the trace terms.  The
 // points are read by prep() and written by finish(), and no other lane touches
 // them.  prep() requests the operands (called before the lane's own mixing, so that
 // their latency overlaps it); finish() sums and writes the results.
@@ -453,8 +459,9 @@ struct MirrorPoints {
     int i, part, kp;
     bool act;
 
-    __device__ __forceinline__ void prep(const cpx<R>* sh, int nz, int e, const UniformBuf<R>& qb0,
-                                         long long colstride, int M, int QY, const R* lpg)
+    __device__ __forceinline__ void prep(const cpx<R>* sh, int nz, int e, const R* __restrict__ Q,
+                                         long long qcs, const int* __restrict__ sl, int QY,
+                                         const R* lpg)
     {
         i = e % NZMAX;
         part = (e / NZMAX) & 1;
@@ -462,14 +469,15 @@ struct MirrorPoints {
         act = pt < 2 && i < nz;
         const int ii = i < nz ? i : nz - 1;
         kp = pt == 1 ? LY / 2 : 0;
-        const unsigned off = (unsigned)(kp + (part ? (long long)M * colstride : 0));
+        const UniformBuf<R> qb0(Q, (unsigned)(2 * qcs * sizeof(R)));
+        const unsigned off = (unsigned)(kp + (part ? qcs : 0LL));
 #pragma unroll
         for (int j = 0; j < NZMAX; ++j) {
             const int jj = j < nz ? j : ii;
             const int a = ii < jj ? ii : jj, b = ii < jj ? jj : ii;
-            // the pair index differs between lanes, so it goes into the lane
-            // offset (the second offset of a buffer load must be wave-uniform)
-            const unsigned o = off + (unsigned)((a * nz - a * (a - 1) / 2 + (b - a)) * 5 * QY);
+            // the row and the slot differ between lanes, so they go into the
+            // lane offset (the second offset of a buffer load must be wave-uniform)
+            const unsigned o = off + (unsigned)(sl[a * nz - a * (a - 1) / 2 + (b - a)] * 5 * QY);
             xx[j] = qb0.ld(o, 0u);
             yy[j] = qb0.ld(o + QY, 0u);
         }
@@ -529,7 +537,7 @@ struct FusedShape {
 template <typename R, int LY, int NZMAX, bool ADJ>
 __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __restrict__ X,
                                             int ny, int nz, int M, const R* __restrict__ Q,
-                                            long long q_geom_stride, int QY,
+                                            long long qcs, const int* __restrict__ qslot, int QY,
                                             const R* __restrict__ lp,
                                             const cpx<R>* __restrict__ twy)
 {
@@ -552,23 +560,21 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
     const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);   // this lane's point
     const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);        // its quadrant column
     const int P = nz * (nz + 1) / 2;
-    const long long colstride = (long long)P * 5 * QY;       // one kx column of the tensor
-    const R* Qg = Q + (long long)geom * q_geom_stride;
-    const unsigned cbytes = (unsigned)(colstride * sizeof(R));
-    const UniformBuf<R> qb(Qg + kx * colstride, cbytes);
-    // packed column: rows kx = 0 and kx = M from one uniform base, the row in
-    // the lane offset
-    const UniformBuf<R> qb0(Qg, (unsigned)((M + 1) * colstride * sizeof(R)));
-    const unsigned off0 = (unsigned)(t + (p == 0 ? 0 : M * colstride));
+    const int* sl = qslot + (long long)geom * P;              // the stack's pair slots
+    const UniformBuf<R> qb(Q + tab_row(kx, M) * qcs, (unsigned)(qcs * sizeof(R)));
+    // packed column: rows kx = 0 and kx = M (adjacent in the table) from one
+    // uniform base, the row in the lane offset
+    const UniformBuf<R> qb0(Q, (unsigned)(2 * qcs * sizeof(R)));
+    const unsigned off0 = (unsigned)(t + (p == 0 ? 0LL : qcs));
     // (above 8 layers, or with 1024 threads per block, the registers do not
     // hold a prefetched row)
     constexpr bool EARLY_ROW = NZMAX <= 8 && NT <= 512;
     TensorRow<R, NZMAX> row0;
     if constexpr (EARLY_ROW) {
         if (kx != 0) {
-            if (t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0);
+            if (t < LY / 2) row0.load(qb, (unsigned)kq, QY, nz, 0, sl);
         } else if (t != 0 && t < LY / 2) {
-            row0.template load<1>(qb0, off0, QY, nz, 0);
+            row0.template load<1>(qb0, off0, QY, nz, 0, sl);
         }
     }
 
@@ -603,7 +609,7 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
     MirrorPoints<R, LY, NZMAX, ADJ> mirror;
     const bool mirror_wave = kx == 0 && tid < 64;
     if (mirror_early && mirror_wave)
-        mirror.prep(sh, nz, tid, qb0, colstride, M, QY, lp + (long long)geom * 2 * nz);
+        mirror.prep(sh, nz, tid, Q, qcs, sl, QY, lp + (long long)geom * 2 * nz);
 
     if (t < LY / 2) {
         const R* lpg = lp + (long long)geom * 2 * nz;
@@ -635,8 +641,8 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
         if (kx != 0) {
             auto in = [&](int c, int l) -> cpx<R> { return ld(c, l, ky); };
-            if constexpr (EARLY_ROW) mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg, row0);
-            else mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sg, dg);
+            if constexpr (EARLY_ROW) mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sl, sg, dg, row0);
+            else mix1<R, NZMAX>(nz, in, H, qb, (unsigned)kq, QY, sl, sg, dg);
             store(ky);
         } else if (t != 0) {
             // column 0 holds Z = A + iB with A the kx = 0 and B the kx = Lx/2
@@ -650,8 +656,8 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
                               : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
             };
             // on the rows kx = 0 and kx = M only xx, yy, zz and yz are non-zero
-            if constexpr (EARLY_ROW) mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg, row0);
-            else mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, R(1), dg);
+            if constexpr (EARLY_ROW) mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, sl, R(1), dg, row0);
+            else mix1<R, NZMAX, 1>(nz, in, H, qb0, off0, QY, sl, R(1), dg);
 #pragma unroll
             for (int k = 0; k < 3 * NZMAX; ++k) {
                 const cpx<R> o = {__shfl_xor(H[k].x, 1), __shfl_xor(H[k].y, 1)};
@@ -663,7 +669,7 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
     }
     if (mirror_wave) {
         if constexpr (!mirror_early)
-            mirror.prep(sh, nz, tid, qb0, colstride, M, QY, lp + (long long)geom * 2 * nz);
+            mirror.prep(sh, nz, tid, Q, qcs, sl, QY, lp + (long long)geom * 2 * nz);
         mirror.finish(sh, nz, lp + (long long)geom * 2 * nz);
     }
     __syncthreads();
@@ -684,12 +690,13 @@ __device__ __forceinline__ void ymix_column(int kx, int b, int geom, cpx<R>* __r
 // buffer descriptor built from its result is treated as a per-lane value).
 template <typename R, int LY, int NZMAX, bool ADJ>
 __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
-    cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long q_geom_stride,
-    int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
+    cpx<R>* __restrict__ X, int ny, int nz, int M, const R* __restrict__ Q, long long qcs,
+    const int* __restrict__ qslot, int QY, const R* __restrict__ lp, int bpg,
+    const cpx<R>* __restrict__ twy)
 {
     const int geom = blockIdx.z;
-    ymix_column<R, LY, NZMAX, ADJ>(blockIdx.x, geom * bpg + blockIdx.y, geom, X, ny, nz, M, Q,
-                                   q_geom_stride, QY, lp, twy);
+    ymix_column<R, LY, NZMAX, ADJ>(blockIdx.x, geom * bpg + blockIdx.y, geom, X, ny, nz, M, Q, qcs,
+                                   qslot, QY, lp, twy);
 }
 
 // ---------------------------------------------------------------------------
@@ -712,8 +719,9 @@ struct ExactShape {
 
 template <typename R, int LY, int NZ, bool ADJ, int PRE = 0>
 __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
-    cpx<R>* __restrict__ X, int ny, int M, const R* __restrict__ Q, long long q_geom_stride,
-    int QY, const R* __restrict__ lp, int bpg, const cpx<R>* __restrict__ twy)
+    cpx<R>* __restrict__ X, int ny, int M, const R* __restrict__ Q, long long qcs,
+    const int* __restrict__ qslot, int QY, const R* __restrict__ lp, int bpg,
+    const cpx<R>* __restrict__ twy)
 {
     constexpr int NT = ExactShape<LY>::NT;
     constexpr int V = fft_vals(LY), GT = LY / V, NG = NT / GT;
@@ -729,7 +737,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
     const int kx = blockIdx.x + (OWN_COL0 ? 0 : 1), geom = blockIdx.z, b = geom * bpg + blockIdx.y;
     if constexpr (OWN_COL0) {
         if (kx == 0) {
-            ymix_column<R, LY, NZ, ADJ>(0, b, geom, X, ny, NZ, M, Q, q_geom_stride, QY, lp, twy);
+            ymix_column<R, LY, NZ, ADJ>(0, b, geom, X, ny, NZ, M, Q, qcs, qslot, QY, lp, twy);
             return;
         }
     }
@@ -740,9 +748,8 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
     const int tid = threadIdx.x, grp = tid / GT, g = tid % GT;
     const int cbytes = ny * (int)sizeof(cpx<R>);
     const int p = tid & 1;
-    const long long colstride = (long long)P * 5 * QY;
-    const UniformBuf<R> qb(Q + (long long)geom * q_geom_stride + kx * colstride,
-                           (unsigned)(colstride * sizeof(R)));
+    const int* sl = qslot + geom * P;  // the stack's pair slots (scalar loads)
+    const UniformBuf<R> qb(Q + (long long)tab_row(kx, M) * qcs, (unsigned)(qcs * sizeof(R)));
     static_assert(PRE == 0 || TPL == 1, "tensor prefetch for one frequency pair per lane");
     R qpre[PRE > 0 ? PRE : 1][5];
 
@@ -771,7 +778,8 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
 #pragma unroll
             for (int u = 0; u < PRE; ++u)
 #pragma unroll
-                for (int c = 0; c < 5; ++c) qpre[u][c] = qb.ld((unsigned)kq, (unsigned)((u * 5 + c) * QY));
+                for (int c = 0; c < 5; ++c)
+                    qpre[u][c] = qb.ld((unsigned)kq, (unsigned)((sl[u] * 5 + c) * QY));
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -811,7 +819,7 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
                     auto q = [&](int c) -> R {
                         if constexpr (PRE > 0)
                             if (u < PRE) return qpre[u < PRE ? u : 0][c];
-                        return qb.ld((unsigned)kq, (unsigned)((u * 5 + c) * QY));
+                        return qb.ld((unsigned)kq, (unsigned)((sl[u] * 5 + c) * QY));
                     };
                     const R xx = q(0), yy = q(1), xy = sg * q(2), xz = q(3), yz = sg * q(4);
                     R zz = -(xx + yy);
@@ -934,8 +942,8 @@ __global__ __launch_bounds__((YPassShape<R, LY>::NT)) void k_yinv(const cpx<R>* 
 template <typename R, int IB>
 __global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ Mh,
                                                     cpx<R>* __restrict__ Hh, int nz, int M, int LY,
-                                                    const R* __restrict__ Q,
-                                                    long long q_geom_stride, int QY,
+                                                    const R* __restrict__ Q, long long qcs,
+                                                    const int* __restrict__ qslot, int QY,
                                                     const R* __restrict__ lp, int bpg, int adjoint,
                                                     int kx0, int nkx, int B)
 {
@@ -955,8 +963,7 @@ __global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ 
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;
     cpx<R>* hb = Hh + ((long long)b * S * M + kx) * LY;
     const R* lpg = lp + (long long)geom * 2 * nz;
-    const R* Qg = Q + (long long)geom * q_geom_stride;
-    const long long colstride = (long long)nz * (nz + 1) / 2 * 5 * QY;
+    const int* sl = qslot + (long long)geom * (nz * (nz + 1) / 2);  // the stack's pair slots
     const R* dg = lpg + nz;
 
     // H[IB][3] += S^{ij} v_j over all sources j; row: tensor row (kx) base,
@@ -972,7 +979,7 @@ __global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ 
                 const int i = i0 + k;
                 if (i < nz) {
                     const int a = i < j ? i : j, bq = i < j ? j : i;
-                    const R* q = row + (long long)(a * nz - a * (a - 1) / 2 + (bq - a)) * 5 * QY + kq;
+                    const R* q = row + (long long)sl[a * nz - a * (a - 1) / 2 + (bq - a)] * 5 * QY + kq;
                     const R simag = i <= j ? R(1) : R(-1);  // conj for the transposed pair
                     const R xx = q[0], yy = q[QY], xy = sg * q[2 * QY], xz = simag * q[3 * QY],
                             yz = sg * simag * q[4 * QY];
@@ -997,12 +1004,13 @@ __global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ 
         const int ky = p == 0 ? t : (t == 0 ? LY / 2 : LY - t);
         const int kq = p == 0 ? t : (t == 0 ? LY / 2 : t);
         const R sg = (p == 1 && t != 0) ? R(-1) : R(1);
-        mix(H, Qg + kx * colstride, kq, sg, [&](int c, int j) { return mb[(c * nz + j) * sst + ky]; });
+        mix(H, Q + tab_row(kx, M) * qcs, kq, sg,
+            [&](int c, int j) { return mb[(c * nz + j) * sst + ky]; });
         store(H, ky);
     } else if (t != 0) {
         // A(t) = (Z(t) + conj Z(-t)) / 2 on lane 0, B(t) = (Z(t) - conj Z(-t)) / (2i) on lane 1
         const int k1 = t, k2 = LY - t;
-        mix(H, Qg + (p == 0 ? 0 : M) * colstride, t, R(1), [&](int c, int j) {
+        mix(H, Q + (p == 0 ? 0 : tab_row(M, M)) * qcs, t, R(1), [&](int c, int j) {
             const cpx<R> z1 = mb[(c * nz + j) * sst + k1], z2 = mb[(c * nz + j) * sst + k2];
             return p == 0 ? cpx<R>{R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y)}
                           : cpx<R>{R(0.5) * (z1.y + z2.y), R(0.5) * (z2.x - z1.x)};
@@ -1021,13 +1029,13 @@ __global__ __launch_bounds__(64, 4) void k_mix_pairs(const cpx<R>* __restrict__ 
         // ky = 0 (lane 0) or LY/2 (lane 1), each its own mirror: A = Re Z, B = Im Z;
         // the point receives A' first and then A' + i B'
         const int kp = p == 0 ? 0 : LY / 2;
-        mix(H, Qg, kp, R(1), [&](int c, int j) { return cpx<R>{mb[(c * nz + j) * sst + kp].x, R(0)}; });
+        mix(H, Q, kp, R(1), [&](int c, int j) { return cpx<R>{mb[(c * nz + j) * sst + kp].x, R(0)}; });
         cpx<R> keep[IB][3];
 #pragma unroll
         for (int k = 0; k < IB; ++k)
 #pragma unroll
             for (int c = 0; c < 3; ++c) keep[k][c] = H[k][c];
-        mix(H, Qg + M * colstride, kp, R(1),
+        mix(H, Q + tab_row(M, M) * qcs, kp, R(1),
             [&](int c, int j) { return cpx<R>{mb[(c * nz + j) * sst + kp].y, R(0)}; });
 #pragma unroll
         for (int k = 0; k < IB; ++k)

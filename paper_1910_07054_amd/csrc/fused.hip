@@ -28,39 +28,39 @@ hipError_t set_lds(const void* kernel, size_t lds)
 }
 
 template <typename R, int LY, int NZMAX, bool ADJ>
-hipError_t fused_a(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+hipError_t fused_a(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qcs, const int* qslot,
                    int QY, const void* lp, const void* tw, hipStream_t s)
 {
     const size_t lds = sizeof(cpx<R>) * 3 * (size_t)nz * fft_region(LY);
     hipError_t e = set_lds((const void*)k_ymix_fused<R, LY, NZMAX, ADJ>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ymix_fused<R, LY, NZMAX, ADJ>), dim3(M, bpg, G), dim3(FusedShape<LY>::NT),
-                       lds, s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qgs, QY, (const R*)lp, bpg,
+                       lds, s, (cpx<R>*)X, ny, nz, M, (const R*)Q, qcs, qslot, QY, (const R*)lp, bpg,
                        (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
 template <typename R, int LY, int NZMAX>
-hipError_t fused_t(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+hipError_t fused_t(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qcs, const int* qslot,
                    int QY, const void* lp, int adjoint, const void* tw, hipStream_t s)
 {
-    if (adjoint) return fused_a<R, LY, NZMAX, true>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    return fused_a<R, LY, NZMAX, false>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    if (adjoint) return fused_a<R, LY, NZMAX, true>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    return fused_a<R, LY, NZMAX, false>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
 }
 
 template <typename R, int LY>
-hipError_t fused_nz(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+hipError_t fused_nz(int nz, void* X, int ny, int M, int bpg, int G, const void* Q, long long qcs, const int* qslot,
                     int QY, const void* lp, int adjoint, const void* tw, hipStream_t s)
 {
     switch (nzmax_for<R>(nz, LY)) {
-    case 4: return fused_t<R, LY, 4>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 4: return fused_t<R, LY, 4>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
     case 8:
         if constexpr (sizeof(R) == 4 && LY < 1024)
-            return fused_t<R, LY, 8>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+            return fused_t<R, LY, 8>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
         return hipErrorInvalidValue;
     case 12:
         if constexpr (sizeof(R) == 4 && LY < 1024)
-            return fused_t<R, LY, 12>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+            return fused_t<R, LY, 12>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -68,18 +68,18 @@ hipError_t fused_nz(int nz, void* X, int ny, int M, int bpg, int G, const void* 
 
 template <typename R>
 hipError_t fused_ly(int LY, int nz, void* X, int ny, int M, int bpg, int G, const void* Q,
-                    long long qgs, int QY, const void* lp, int adjoint, const void* tw,
+                    long long qcs, const int* qslot, int QY, const void* lp, int adjoint, const void* tw,
                     hipStream_t s)
 {
     switch (LY) {
-    case 8: return fused_nz<R, 8>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 16: return fused_nz<R, 16>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 32: return fused_nz<R, 32>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 64: return fused_nz<R, 64>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 128: return fused_nz<R, 128>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 256: return fused_nz<R, 256>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 512: return fused_nz<R, 512>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
-    case 1024: return fused_nz<R, 1024>(nz, X, ny, M, bpg, G, Q, qgs, QY, lp, adjoint, tw, s);
+    case 8: return fused_nz<R, 8>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 16: return fused_nz<R, 16>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 32: return fused_nz<R, 32>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 64: return fused_nz<R, 64>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 128: return fused_nz<R, 128>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 256: return fused_nz<R, 256>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 512: return fused_nz<R, 512>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
+    case 1024: return fused_nz<R, 1024>(nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, tw, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -96,7 +96,7 @@ bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes)
 }
 
 hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
-                        long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
+                        long long qcs, const int* qslot, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s, bool generic)
 {
     (void)QX;
@@ -104,10 +104,10 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
     if (bpg < 1 || B % bpg != 0) return hipErrorInvalidValue;
     const int G = B / bpg;
     if (!generic && fused_exact_supported(fp64, LY, nz))
-        return launch_fused_exact(LY, nz, adjoint, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, twy, s);
+        return launch_fused_exact(LY, nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, twy, s);
     if (fp64)
-        return fused_ly<double>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);
-    return fused_ly<float>(LY, nz, X, ny, M, bpg, G, Q, q_geom_stride, QY, lp, adjoint, twy, s);
+        return fused_ly<double>(LY, nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, twy, s);
+    return fused_ly<float>(LY, nz, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, adjoint, twy, s);
 }
 
 }  // namespace hfd

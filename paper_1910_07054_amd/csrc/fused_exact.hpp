@@ -8,7 +8,7 @@
 namespace hfd {
 
 template <int LY, int NZ, bool ADJ>
-hipError_t fused_exact_a(void* X, int ny, int M, int bpg, int G, const void* Q, long long qgs,
+hipError_t fused_exact_a(void* X, int ny, int M, int bpg, int G, const void* Q, long long qcs, const int* qslot,
                          int QY, const void* lp, const void* tw, hipStream_t s)
 {
     const size_t lds = sizeof(cpx<float>) * 3 * (size_t)NZ * fft_region(LY);
@@ -23,12 +23,12 @@ hipError_t fused_exact_a(void* X, int ny, int M, int bpg, int G, const void* Q, 
     }
     hipLaunchKernelGGL((k_ymix_fused_nz<float, LY, NZ, ADJ>), dim3(own_col0 ? M : M - 1, bpg, G),
                        dim3(ExactShape<LY>::NT), lds, s, (cpx<float>*)X, ny, M, (const float*)Q,
-                       qgs, QY, (const float*)lp, bpg, (const cpx<float>*)tw);
+                       qcs, qslot, QY, (const float*)lp, bpg, (const cpx<float>*)tw);
     if constexpr (!own_col0) {
         // the packed column 0 (kx = 0 and Lx/2) by the generic kernel
         static_assert(NZ <= 4, "generic 1024-point column kernel holds up to 4 layers");
         hipLaunchKernelGGL((k_ymix_fused<float, LY, 4, ADJ>), dim3(1, bpg, G), dim3(FusedShape<LY>::NT),
-                           lds, s, (cpx<float>*)X, ny, NZ, M, (const float*)Q, qgs, QY,
+                           lds, s, (cpx<float>*)X, ny, NZ, M, (const float*)Q, qcs, qslot, QY,
                            (const float*)lp, bpg, (const cpx<float>*)tw);
     }
     return hipGetLastError();
@@ -36,10 +36,10 @@ hipError_t fused_exact_a(void* X, int ny, int M, int bpg, int G, const void* Q, 
 
 template <int LY, int NZ>
 hipError_t fused_exact_t(int adjoint, void* X, int ny, int M, int bpg, int G, const void* Q,
-                         long long qgs, int QY, const void* lp, const void* tw, hipStream_t s)
+                         long long qcs, const int* qslot, int QY, const void* lp, const void* tw, hipStream_t s)
 {
-    if (adjoint) return fused_exact_a<LY, NZ, true>(X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    return fused_exact_a<LY, NZ, false>(X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    if (adjoint) return fused_exact_a<LY, NZ, true>(X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    return fused_exact_a<LY, NZ, false>(X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
 }
 
 }  // namespace hfd

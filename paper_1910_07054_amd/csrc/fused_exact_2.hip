@@ -4,13 +4,13 @@
 namespace hfd {
 
 hipError_t launch_fused_exact_2(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                   const void* Q, long long qgs, int QY, const void* lp,
+                                   const void* Q, long long qcs, const int* qslot, int QY, const void* lp,
                                    const void* tw, hipStream_t s)
 {
     switch (nz) {
-    case 5: return fused_exact_t<512, 5>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 6: return fused_exact_t<512, 6>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 7: return fused_exact_t<512, 7>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 5: return fused_exact_t<512, 5>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    case 6: return fused_exact_t<512, 6>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    case 7: return fused_exact_t<512, 7>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -4,14 +4,14 @@
 namespace hfd {
 
 hipError_t launch_fused_exact_4(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                   const void* Q, long long qgs, int QY, const void* lp,
+                                   const void* Q, long long qcs, const int* qslot, int QY, const void* lp,
                                    const void* tw, hipStream_t s)
 {
     switch (nz) {
-    case 1: return fused_exact_t<1024, 1>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 2: return fused_exact_t<1024, 2>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 3: return fused_exact_t<1024, 3>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    case 4: return fused_exact_t<1024, 4>(adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    case 1: return fused_exact_t<1024, 1>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    case 2: return fused_exact_t<1024, 2>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    case 3: return fused_exact_t<1024, 3>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    case 4: return fused_exact_t<1024, 4>(adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

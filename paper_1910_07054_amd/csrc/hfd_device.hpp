@@ -38,6 +38,11 @@ __device__ __forceinline__ cpx<R> mul_mi(cpx<R> a)
     return INV ? cpx<R>{-a.y, a.x} : cpx<R>{a.y, -a.x};
 }
 
+// Row order of the tensor tables (the Fourier tensor's pair slots and the
+// derivative offsets): kx = 0, kx = M = Lx/2, then kx = 1 .. M - 1, so that
+// the two rows the packed column 0 reads are adjacent.
+__host__ __device__ inline int tab_row(int kx, int M) { return kx == 0 ? 0 : (kx == M ? 1 : kx + 1); }
+
 // Ordering point for LDS traffic inside one wavefront.
 __device__ __forceinline__ void wave_sync()
 {

@@ -44,55 +44,62 @@ hipError_t launch_yfwd(bool fp64, int LY, const void* in, void* out, int n_in, l
 hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, long long ncols,
                        const void* twy, hipStream_t s);
 
+// The Fourier tensor of a plan is one table of pair slots, Q[QX][nslot][5][QY]
+// (kx row outer, qcs = nslot * 5 * QY elements per row); pair u (i <= j,
+// u = i nz - i (i - 1) / 2 + j - i) of stack g reads slot qslot[g * P + u].
+// Stacks that share a pair geometry (thicknesses and offset) share its slot.
+// Consumers take (Q, qcs, qslot) with qslot already offset to their first
+// stack.
+
 // fused y pass: does a compiled instance exist for (fp64, LY, nz) with lds bytes?
 bool fused_supported(bool fp64, int LY, int nz, size_t* lds_bytes);
 // generic = true: the run-time layer-count kernel even where an exact-layer
 // kernel exists (the autotuner times both)
 hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B, const void* Q,
-                        long long q_geom_stride, int QX, int QY, const void* lp, int bpg,
+                        long long qcs, const int* qslot, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s, bool generic = false);
 
 // exact-layer-count fused y pass (single precision; LY = 512 with 1 <= nz <=
 // 10, LY = 1024 with 1 <= nz <= 4): grid (M, bpg, G); units 1-3 cover 1-4, 5-7
 // and 8-10 layers of 512-point columns, unit 4 the 1024-point columns
 hipError_t launch_fused_exact_1(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                const void* Q, long long qgs, int QY, const void* lp,
-                                const void* tw, hipStream_t s);
+                                const void* Q, long long qcs, const int* qslot, int QY,
+                                const void* lp, const void* tw, hipStream_t s);
 hipError_t launch_fused_exact_2(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                const void* Q, long long qgs, int QY, const void* lp,
-                                const void* tw, hipStream_t s);
+                                const void* Q, long long qcs, const int* qslot, int QY,
+                                const void* lp, const void* tw, hipStream_t s);
 hipError_t launch_fused_exact_3(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                const void* Q, long long qgs, int QY, const void* lp,
-                                const void* tw, hipStream_t s);
+                                const void* Q, long long qcs, const int* qslot, int QY,
+                                const void* lp, const void* tw, hipStream_t s);
 hipError_t launch_fused_exact_4(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
-                                const void* Q, long long qgs, int QY, const void* lp,
-                                const void* tw, hipStream_t s);
+                                const void* Q, long long qcs, const int* qslot, int QY,
+                                const void* lp, const void* tw, hipStream_t s);
 inline bool fused_exact_supported(bool fp64, int LY, int nz)
 {
     return !fp64 && nz >= 1 && ((LY == 512 && nz <= 10) || (LY == 1024 && nz <= 4));
 }
 inline hipError_t launch_fused_exact(int LY, int nz, int adjoint, void* X, int ny, int M, int bpg,
-                                     int G, const void* Q, long long qgs, int QY, const void* lp,
-                                     const void* tw, hipStream_t s)
+                                     int G, const void* Q, long long qcs, const int* qslot, int QY,
+                                     const void* lp, const void* tw, hipStream_t s)
 {
-    if (LY == 1024) return launch_fused_exact_4(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    if (nz <= 4) return launch_fused_exact_1(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    if (nz <= 7) return launch_fused_exact_2(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
-    return launch_fused_exact_3(nz, adjoint, X, ny, M, bpg, G, Q, qgs, QY, lp, tw, s);
+    if (LY == 1024) return launch_fused_exact_4(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    if (nz <= 4) return launch_fused_exact_1(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    if (nz <= 7) return launch_fused_exact_2(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    return launch_fused_exact_3(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
 }
 
 // generic mixing of the kx columns [kx0, kx0 + nkx)
 hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
-                              const void* Q, long long q_geom_stride, int QX, int QY, const void* lp,
-                              int bpg, int adjoint, int kx0, int nkx, hipStream_t s);
+                              const void* Q, long long qcs, const int* qslot, int QX, int QY,
+                              const void* lp, int bpg, int adjoint, int kx0, int nkx, hipStream_t s);
 
 // batched mixing of the kx columns 1 .. M-1 (all states of one stack per block,
 // 16 at a time): matrix cores with the three-way BF16 split (mfma = true) or
 // FP32 VALU on the same staging
 bool mix_batched_supported(int nz, int B, int G);
 hipError_t launch_mix_batched(bool mfma, const void* Mh, void* Hh, int nz, int M, int LY, int B,
-                              const void* Q, long long q_geom_stride, int QY, const void* lp, int bpg,
-                              int adjoint, hipStream_t s);
+                              const void* Q, long long qcs, const int* qslot, int QY, const void* lp,
+                              int bpg, int adjoint, hipStream_t s);
 
 // equidistant stacks: 3-D Fourier tensor from the per-offset 2D spectra, and
 // the z pass on the five-pass spectra (packed column unpacked into Bc and
@@ -126,7 +133,7 @@ __host__ __device__ inline ITabLayout itab_layout(int nz)
     return t;
 }
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, int nzt,
+                        int nb, const void* Q, long long qcs, const int* qslot, const void* D, int nzt,
                         const int* itab, int itab_stride, const void* lp, int bpg,
                         int QX, int QY, double* partial, hipStream_t s);
 hipError_t launch_tgrad_finish(const double* partial, int nparts, int B, int nz, const int* itab,

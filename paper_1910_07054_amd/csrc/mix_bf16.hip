@@ -105,7 +105,8 @@ template <bool MFMA, int NZ>
 __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restrict__ Mh,
                                                      cpx<float>* __restrict__ Hh, int M, int LY,
                                                      const float* __restrict__ Q,
-                                                     long long q_geom_stride, int QY,
+                                                     long long qcs, const int* __restrict__ qslot,
+                                                     int QY,
                                                      const float* __restrict__ lp, int bpg,
                                                      int adjoint)
 {
@@ -126,13 +127,14 @@ __global__ __launch_bounds__(256) void k_mix_batched(const cpx<float>* __restric
     // tensor quadrant values; the ky-odd components (xy, yz) change sign for
     // ky > LY/2.  The sign is applied as a bit flip: a nested conditional
     // negation here was compiled with the xy case dropped.
-    const float* Qcol = Q + (long long)geom * q_geom_stride + (long long)kx * P * 5 * QY;
+    const float* Qcol = Q + (long long)tab_row(kx, M) * qcs;
+    const int* sl = qslot + geom * P;  // the stack's pair slots
     for (int idx = tid; idx < TK * P * 5; idx += 256) {
         const int kyl = idx % TK, c = (idx / TK) % 5, u = idx / (TK * 5);
         const int ky = ky0 + kyl;
         const int kq = ky <= LY / 2 ? ky : LY - ky;
         float v = 0.f;
-        if (ky < LY) v = Qcol[(long long)(u * 5 + c) * QY + kq];
+        if (ky < LY) v = Qcol[(long long)(sl[u] * 5 + c) * QY + kq];
         // c in {2, 4}: even and non-zero
         const unsigned flip = (unsigned)(ky > LY / 2) & (unsigned)((c & 1) == 0) & (unsigned)(c != 0);
         st[(kyl * P + u) * 5 + c] = __uint_as_float(__float_as_uint(v) ^ (flip << 31));
@@ -277,8 +279,8 @@ namespace {
 
 template <bool MFMA, int NZ>
 hipError_t launch_batched_nz(const void* Mh, void* Hh, int M, int LY, int G, const void* Q,
-                             long long qgs, int QY, const void* lp, int bpg, int adjoint,
-                             hipStream_t s)
+                             long long qcs, const int* qslot, int QY, const void* lp, int bpg,
+                             int adjoint, hipStream_t s)
 {
     using SH = BatchedShape<NZ>;
     const size_t lds = SH::lds(MFMA);
@@ -286,39 +288,43 @@ hipError_t launch_batched_nz(const void* Mh, void* Hh, int M, int LY, int G, con
     if (e != hipSuccess) return e;
     dim3 grid((LY + SH::TK - 1) / SH::TK, M - 1, G);
     hipLaunchKernelGGL((k_mix_batched<MFMA, NZ>), grid, dim3(256), lds, s, (const cpx<float>*)Mh,
-                       (cpx<float>*)Hh, M, LY, (const float*)Q, qgs, QY, (const float*)lp, bpg,
-                       adjoint);
+                       (cpx<float>*)Hh, M, LY, (const float*)Q, qcs, qslot, QY, (const float*)lp,
+                       bpg, adjoint);
     return hipGetLastError();
 }
 
 template <bool MFMA>
 hipError_t launch_batched(int nz, const void* Mh, void* Hh, int M, int LY, int G, const void* Q,
-                          long long qgs, int QY, const void* lp, int bpg, int adjoint, hipStream_t s)
+                          long long qcs, const int* qslot, int QY, const void* lp, int bpg,
+                          int adjoint, hipStream_t s)
 {
+#define HFD_BATCHED_CASE(N) \
+    case N: return launch_batched_nz<MFMA, N>(Mh, Hh, M, LY, G, Q, qcs, qslot, QY, lp, bpg, adjoint, s)
     switch (nz) {
-    case 1: return launch_batched_nz<MFMA, 1>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 2: return launch_batched_nz<MFMA, 2>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 3: return launch_batched_nz<MFMA, 3>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 4: return launch_batched_nz<MFMA, 4>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 5: return launch_batched_nz<MFMA, 5>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 6: return launch_batched_nz<MFMA, 6>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 7: return launch_batched_nz<MFMA, 7>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
-    case 8: return launch_batched_nz<MFMA, 8>(Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
+    HFD_BATCHED_CASE(1);
+    HFD_BATCHED_CASE(2);
+    HFD_BATCHED_CASE(3);
+    HFD_BATCHED_CASE(4);
+    HFD_BATCHED_CASE(5);
+    HFD_BATCHED_CASE(6);
+    HFD_BATCHED_CASE(7);
+    HFD_BATCHED_CASE(8);
     default: return hipErrorInvalidValue;
     }
+#undef HFD_BATCHED_CASE
 }
 
 }  // namespace
 
 hipError_t launch_mix_batched(bool mfma, const void* Mh, void* Hh, int nz, int M, int LY, int B,
-                              const void* Q, long long qgs, int QY, const void* lp, int bpg,
-                              int adjoint, hipStream_t s)
+                              const void* Q, long long qcs, const int* qslot, int QY, const void* lp,
+                              int bpg, int adjoint, hipStream_t s)
 {
     if (M < 2) return hipSuccess;
     if (bpg < 1 || B % bpg) return hipErrorInvalidValue;
     const int G = B / bpg;
-    return mfma ? launch_batched<true>(nz, Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s)
-                : launch_batched<false>(nz, Mh, Hh, M, LY, G, Q, qgs, QY, lp, bpg, adjoint, s);
+    return mfma ? launch_batched<true>(nz, Mh, Hh, M, LY, G, Q, qcs, qslot, QY, lp, bpg, adjoint, s)
+                : launch_batched<false>(nz, Mh, Hh, M, LY, G, Q, qcs, qslot, QY, lp, bpg, adjoint, s);
 }
 
 }  // namespace hfd

@@ -580,7 +580,7 @@ __global__ __launch_bounds__((TabShape<LY>::NT)) void k_ytab(
         const int oc = comps == 6 ? c6 : (c6 < 2 ? c6 : (c6 == 2 ? -1 : c6 - 1));
         if (oc < 0) return;
         const long long o = row_outer
-            ? (((long long)kx * pair_total + pair0 + u) * comps + oc) * QY + ky
+            ? (((long long)tab_row(kx, M) * pair_total + pair0 + u) * comps + oc) * QY + ky
             : (((long long)u * comps + oc) * QX + kx) * QY + ky;
         Qout[o] = (R)(v * sc);
     };

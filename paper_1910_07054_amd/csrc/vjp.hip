@@ -98,13 +98,13 @@ __device__ inline void load_chunk(const int* __restrict__ src, int (&dst)[QC])
 template <typename R, int QC, bool PACKED>
 __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __restrict__ gb,
                                  long long sst, int nz, int M, int kx, int ky, int kyn, int kq,
-                                 double sgy, double wgt0, const R* __restrict__ Qg,
-                                 const R* __restrict__ Dg, int nzt, const int* __restrict__ it,
+                                 double sgy, double wgt0, const R* __restrict__ Q, long long qcs,
+                                 const int* __restrict__ sl, const R* __restrict__ Dg, int nzt,
+                                 const int* __restrict__ it,
                                  const R* __restrict__ lpg, int QY, double* __restrict__ acc)
 {
     constexpr int NV = PACKED ? 2 : 1;  // raw spectrum values per entry (ky, and LY - ky)
     const int lane = threadIdx.x;
-    const int P = nz * (nz + 1) / 2;
     const ITabLayout lay = itab_layout(nz);
     const int NI = it[0];
     const int* pinfo = it + lay.info;
@@ -115,10 +115,11 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
     auto add_out = [&](int v, double val) { atomicAdd(&acc[v * 64 + lane], val); };
     for (int ps = 0; ps < NV; ++ps) {
         const int row = PACKED ? (ps ? M : 0) : kx;
-        // rows of D ([QX][nzt][6][QY]) and Q ([QX][P][5][QY]) as buffers: the
-        // lane offset is kq, the slot / pair and component offsets are scalar
-        const UniformBuf<R> dbuf(Dg + (long long)row * nzt * 6 * QY, (unsigned)(nzt * 6 * QY * sizeof(R)));
-        const UniformBuf<R> qbuf(Qg + (long long)row * P * 5 * QY, (unsigned)(P * 5 * QY * sizeof(R)));
+        // rows of D ([QX][nzt][6][QY]) and of the tensor table ([QX][slots][5][QY])
+        // as buffers: the lane offset is kq, the slot and component offsets are scalar
+        const int trow = tab_row(row, M);
+        const UniformBuf<R> dbuf(Dg + (long long)trow * nzt * 6 * QY, (unsigned)(nzt * 6 * QY * sizeof(R)));
+        const UniformBuf<R> qbuf(Q + (long long)trow * qcs, (unsigned)(qcs * sizeof(R)));
         // component c of layer l: raw loads, then (re, im) at this point
         auto raw = [&](const cpx<R>* base, int c, int l, cpx<R> (&z)[NV]) {
             z[0] = base[(c * nz + l) * sst + ky];
@@ -262,9 +263,9 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
                 for (int q = 0; q < QC; ++q) {
                     const int j = jc + q < nz ? jc + q : nz - 1;
                     const int a = l < j ? l : j, bq = l < j ? j : l;
-                    const int u = a * nz - a * (a - 1) / 2 + (bq - a);
+                    const int slot = sl[a * nz - a * (a - 1) / 2 + (bq - a)];
 #pragma unroll
-                    for (int c = 0; c < 5; ++c) f.a[q][c] = qbuf.ld(kq, (unsigned)((u * 5 + c) * QY));
+                    for (int c = 0; c < 5; ++c) f.a[q][c] = qbuf.ld(kq, (unsigned)((slot * 5 + c) * QY));
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) raw(gb, c, l, f.g[c]);
@@ -318,7 +319,8 @@ __device__ inline void tgrad_row(const cpx<R>* __restrict__ mb, const cpx<R>* __
 template <typename R, int QC>
 __global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
                                               const cpx<R>* __restrict__ Gh, int nz, int M, int LY,
-                                              const R* __restrict__ Q, long long qgs,
+                                              const R* __restrict__ Q, long long qcs,
+                                              const int* __restrict__ qslot,
                                               const R* __restrict__ D, int nzt,
                                               const int* __restrict__ itab, int itab_stride,
                                               const R* __restrict__ lp, int bpg,
@@ -345,18 +347,18 @@ __global__ __launch_bounds__(64) void k_tgrad(const cpx<R>* __restrict__ Mh,
     const long long sst = (long long)M * LY;
     const cpx<R>* mb = Mh + ((long long)b * S * M + kx) * LY;
     const cpx<R>* gb = Gh + ((long long)b * S * M + kx) * LY;
-    const R* Qg = Q + (long long)geom * qgs;
+    const int* sl = qslot + (long long)geom * (nz * (nz + 1) / 2);  // the stack's pair slots
     const R* lpg = lp + (long long)geom * 2 * nz;
     const int* it = itab + (long long)geom * itab_stride;
     const int NI = it[0], NS = 2 * nz;
     extern __shared__ double acc[];  // [NI][64]
     for (int v = 0; v < NI; ++v) acc[v * 64 + lane] = 0.0;
     if (kx == 0)
-        tgrad_row<R, QC, true>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 1.0 : 0.0, Qg, D,
-                               nzt, it, lpg, QY, acc);
+        tgrad_row<R, QC, true>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 1.0 : 0.0, Q, qcs,
+                               sl, D, nzt, it, lpg, QY, acc);
     else
-        tgrad_row<R, QC, false>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 2.0 : 0.0, Qg,
-                                D, nzt, it, lpg, QY, acc);
+        tgrad_row<R, QC, false>(mb, gb, sst, nz, M, kx, ky, kyn, kq, sgy, active ? 2.0 : 0.0, Q,
+                                qcs, sl, D, nzt, it, lpg, QY, acc);
     __syncthreads();
     double* out = partial + ((long long)b * ntiles + tile) * NS;
     for (int v = 0; v < NI; ++v) {
@@ -399,17 +401,16 @@ int tgrad_tiles(int M, int LY)
 }
 
 hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M, int LY, int b0,
-                        int nb, const void* Q, long long qgs, const void* D, int nzt,
+                        int nb, const void* Q, long long qcs, const int* qslot, const void* D, int nzt,
                         const int* itab, int itab_stride, const void* lp, int bpg,
                         int QX, int QY, double* partial, hipStream_t s)
 {
     if (nz < 1 || nz > 64 || nb < 1 || bpg < 1 || nb % bpg || LY < 2 || (LY & (LY - 1)))
         return hipErrorInvalidValue;
-    (void)QX;  // D and Q rows are addressed through nzt and QY
+    (void)QX;  // D and Q rows are addressed through nzt, qcs and QY
     // one row of D or Q is a buffer with 32-bit byte offsets
     const long long rsz = fp64 ? 8 : 4;
-    if ((long long)nzt * 6 * QY * rsz >= (1LL << 31) ||
-        (long long)nz * (nz + 1) / 2 * 5 * QY * rsz >= (1LL << 31))
+    if ((long long)nzt * 6 * QY * rsz >= (1LL << 31) || qcs * rsz >= (1LL << 31))
         return hipErrorInvalidValue;
     const int ntiles = tgrad_tiles(M, LY);
     const long long nblk = (long long)((ntiles + 7) / 8) * 8 * nb;
@@ -418,12 +419,12 @@ hipError_t launch_tgrad(bool fp64, const void* Mh, const void* Gh, int nz, int M
     if (fp64)
         hipLaunchKernelGGL((k_tgrad<double, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<double>*)Mh, (const cpx<double>*)Gh, nz, M, LY,
-                           (const double*)Q, qgs, (const double*)D, nzt, itab, itab_stride,
+                           (const double*)Q, qcs, qslot, (const double*)D, nzt, itab, itab_stride,
                            (const double*)lp, bpg, QY, b0, nb, ntiles, partial);
     else
         hipLaunchKernelGGL((k_tgrad<float, 4>), dim3((unsigned)nblk), dim3(64), lds, s,
                            (const cpx<float>*)Mh, (const cpx<float>*)Gh, nz, M, LY,
-                           (const float*)Q, qgs, (const float*)D, nzt, itab, itab_stride,
+                           (const float*)Q, qcs, qslot, (const float*)D, nzt, itab, itab_stride,
                            (const float*)lp, bpg, QY, b0, nb, ntiles, partial);
     return hipGetLastError();
 }

@@ -68,8 +68,8 @@ hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, 
 }
 
 hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
-                              const void* Q, long long qgs, int QX, int QY, const void* lp,
-                              int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
+                              const void* Q, long long qcs, const int* qslot, int QX, int QY,
+                              const void* lp, int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
 {
     (void)QX;
     if (nkx <= 0) return hipSuccess;
@@ -81,12 +81,12 @@ hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M
     dim3 grid((unsigned)nblk);
     if (fp64)
         hipLaunchKernelGGL((k_mix_pairs<double, IB>), grid, dim3(64), 0, s,
-                           (const cpx<double>*)Mh, (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qgs,
-                           QY, (const double*)lp, bpg, adjoint, kx0, nkx, B);
+                           (const cpx<double>*)Mh, (cpx<double>*)Hh, nz, M, LY, (const double*)Q, qcs,
+                           qslot, QY, (const double*)lp, bpg, adjoint, kx0, nkx, B);
     else
         hipLaunchKernelGGL((k_mix_pairs<float, IB>), grid, dim3(64), 0, s,
-                           (const cpx<float>*)Mh, (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qgs, QY,
-                           (const float*)lp, bpg, adjoint, kx0, nkx, B);
+                           (const cpx<float>*)Mh, (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qcs,
+                           qslot, QY, (const float*)lp, bpg, adjoint, kx0, nkx, B);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ class Info(ctypes.Structure):
                 ("Ly", ctypes.c_int), ("fused", ctypes.c_int), ("fp64", ctypes.c_int),
                 ("mix_bf16", ctypes.c_int), ("tensor_bytes", ctypes.c_longlong),
                 ("work_bytes", ctypes.c_longlong), ("equidistant", ctypes.c_int),
-                ("Lz", ctypes.c_int)]
+                ("Lz", ctypes.c_int), ("tensor_slots", ctypes.c_int)]
 
 
 _lib = None
