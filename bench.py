@@ -91,6 +91,18 @@ def algorithmic_bytes(nx, ny, nz, B, G=1):
     return B * 24 * nx * ny * nz + G * 24 * (nx + 1) * (ny + 1) * P
 
 
+def with_distinct_tensor(roof, nx, ny, nz, B, slots):
+    """Add to a roofline record the bytes with the tensor counted once per
+    distinct pair geometry of all stacks (`slots`: stacks that differ in one
+    layer share the other pairs, and the plan stores and reads them once) and
+    the dominant kernel's fraction of HBM peak on those bytes."""
+    b = B * 24 * nx * ny * nz + 24 * (nx + 1) * (ny + 1) * slots
+    roof["tensor_slots"] = slots
+    roof["alg_bytes_distinct"] = b
+    roof["frac_distinct"] = b / (roof["kernel_ms"] * 1e-3) / (HBM_PEAK_GBPS * 1e9)
+    return roof
+
+
 def algorithmic_flops(nx, ny, nz, B):
     """FP32 flops per launch: the pruned 2D FFTs (5 N log2 N convention) of
     the 3 nz input and output signals and the explicit layer sum, 36 nz^2
@@ -501,8 +513,10 @@ def measure_config(name, steps, warmup, stream):
            "cell_updates_per_s": B * wl.nx * wl.ny * wl.nz / (ms * 1e-3),
            "path": tune.split("-> ")[-1], "stage_ms": stages, "setup_s": setup_s,
            "err_vs_fp64_oracle": err,
-           "roofline": roofline_of(stages, algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, G),
-                                   algorithmic_flops(wl.nx, wl.ny, wl.nz, B), ms)}
+           "roofline": with_distinct_tensor(
+               roofline_of(stages, algorithmic_bytes(wl.nx, wl.ny, wl.nz, B, G),
+                           algorithmic_flops(wl.nx, wl.ny, wl.nz, B), ms),
+               wl.nx, wl.ny, wl.nz, B, inf.tensor_slots)}
     if name == "C5":
         res["vjp"] = time_vjp(wl, m, 10, 2, stream)
     del graph
@@ -607,6 +621,7 @@ def main():
     kbytes = fused_kernel_bytes(wl.nx, wl.ny, wl.nz, B, inf.Lx, inf.Ly) if dom == "ymix_fused" else None
     roof = roofline_of(stages, alg_bytes, alg_flops, stats["median"] if stats else ms_per_step / B,
                        kbytes)
+    with_distinct_tensor(roof, wl.nx, wl.ny, wl.nz, B, inf.tensor_slots)
     roof["traffic"] = measured_traffic(args.workload) if dom == "ymix_fused" else None
     roof["traffic_unit"] = "bytes per launch of the dominant kernel (copy-calibrated FETCH_SIZE + WRITE_SIZE)"
 

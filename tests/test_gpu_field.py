@@ -140,6 +140,39 @@ def test_fourier_tensor_matches_oracle(fp64):
     plan.destroy()
 
 
+def test_stacks_share_pair_slots():
+    """Three stacks of four layers: the second differs from the first in the
+    top layer only, the third repeats the first.  Each distinct pair geometry
+    (t_i, t_j, z_i - z_j) of all stacks is stored once (14 of the 30 pairs);
+    each stack's exported tensor, gathered from the shared slots, equals the
+    tensor of a plan that holds that stack alone, and each stack's field
+    matches the brute-force oracle."""
+    import torch
+    nx, ny, dx, dy = 14, 11, 2.5, 2.0
+    t1 = np.array([1.0, 0.7, 2.3, 1.5])
+    t2 = np.array([1.0, 0.7, 2.3, 1.2])
+    gaps = [0.5, 0.0, 0.3]
+    t = np.stack([t1, t2, t1])
+    z = np.stack([W.stack_bottoms(t1, gaps), W.stack_bottoms(t2, gaps), W.stack_bottoms(t1, gaps)])
+    keys = {(t[g, i], t[g, j], z[g, i] - z[g, j]) for g in range(3) for i in range(4) for j in range(i, 4)}
+    assert len(keys) == 14
+    plan = hfd.Plan(nx, ny, dx, dy, t, z, batch_max=3)
+    assert plan.info().tensor_slots == 14
+    for g in range(3):
+        alone = hfd.Plan(nx, ny, dx, dy, t[g], z[g])
+        ref = alone.export_fourier_tensor().astype(np.float64)
+        got = plan.export_fourier_tensor(g).astype(np.float64)
+        alone.destroy()
+        assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max(), g
+    m = np.random.default_rng(45).standard_normal((3, 3, 4, ny, nx))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    h = plan.field(torch.from_numpy(m.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    for g in range(3):
+        ref = oracle.field(nx, ny, dx, dy, z[g], t[g], m[g])
+        assert rel_err(h[g], ref) < 1e-5, g
+    plan.destroy()
+
+
 # ---------------------------------------------------------------------------
 # Forward 2D transform of the zero-padded magnetization
 # ---------------------------------------------------------------------------
