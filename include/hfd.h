@@ -109,7 +109,13 @@ enum {
  * of the dipole kernel beyond six cell sizes (where the 64-term Newell sum
  * loses its digits to cancellation); then a 2D FFT per pair (F1 F2 of Sec.
  * 3.1) in FP64, rounded to the plan's precision.  Only the unique pairs
- * i <= j are stored (reciprocity t_i N^{ij}(d) = t_j N^{ji}(-d)).
+ * i <= j are stored (reciprocity t_i N^{ij}(d) = t_j N^{ji}(-d)), and a pair
+ * geometry (both thicknesses and the offset) that occurs several times, in
+ * one stack or in several, is computed and stored once (hfd_info.tensor_slots
+ * counts them): thickness candidates that differ in one layer share the
+ * tensors of all other pairs.  Memory is reserved for n_geom * nz (nz + 1) / 2
+ * pair tensors, so hfd_set_thickness never reallocates it; a kx row of that
+ * table must stay below 2 GiB (else HFD_ENOTSUP).
  */
 hfd_status hfd_setup_tensor(hfd_plan *out, int nx, int ny, double dx, double dy, int nz,
                             const double *thickness, const double *z_bottom, int n_geom,
