@@ -85,6 +85,17 @@ def test_setup_rejects_invalid_arguments(kw, frag):
     assert frag.lower() in msg.lower()
 
 
+def test_setup_rejects_a_tensor_row_beyond_2_gib():
+    """The pair-slot table reserves n_geom * nz (nz + 1) / 2 pair tensors per
+    kx row: 4096 stacks of 64 layers on 2048-cell rows would need 349 GB per
+    row, beyond the kernels' 32-bit offsets; refused on the host before any
+    device call."""
+    nz, g = 64, 4096
+    st, msg = _setup(nx=2048, ny=2048, nz=nz, thickness=np.ones((g, nz)), n_geom=g, batch_max=g)
+    assert st == hfd.HFD_ENOTSUP
+    assert "2 gib" in msg.lower()
+
+
 def test_null_and_unknown_handles_rejected():
     lib = _lib()
     assert lib.hfd_demag_field(None, 16, 16, 1, None) == hfd.HFD_EHANDLE
