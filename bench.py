@@ -297,9 +297,10 @@ def replay_ms(fn, steps, warmup, stream):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def compare_paths(wl, m, steps, warmup, stream):
-    """Every field path on the same states: one plan per path, B states per
-    call, plus the plain single-state form (B calls of one state)."""
+def compare_paths(wl, m, steps, warmup, stream, only=None):
+    """Every field path (or the ones named in `only`) on the same states: one
+    plan per path, B states per call, plus the plain single-state form (B calls
+    of one state)."""
     import torch
     from paper_1910_07054_amd import hfd
     B = wl.batch
@@ -319,6 +320,8 @@ def compare_paths(wl, m, steps, warmup, stream):
                 ("five_pass_batched_fp32", hfd.HFD_MIX_BATCHED_FP32),
                 ("five_pass_split_bf16_mfma", hfd.HFD_MIX_SPLIT_BF16)]
     for name, fl in variants:
+        if only is not None and name not in only:
+            continue
         plan = hfd.Plan(wl.nx, wl.ny, wl.dx, wl.dy, wl.thickness, wl.z_bottom, batch_max=B, flags=fl)
         # each variant with its own tuned x tile (and, on the fused path, state
         # runs and kernel); the path itself stays the one the flags select
@@ -519,6 +522,15 @@ def measure_config(name, steps, warmup, stream):
                wl.nx, wl.ny, wl.nz, B, inf.tensor_slots)}
     if name == "C5":
         res["vjp"] = time_vjp(wl, m, 10, 2, stream)
+    if name == "C3":
+        # the batched launch against the plain single-state form, and the
+        # split-BF16 matrix-core mixing beside it, on the same 64 states
+        forms = compare_paths(wl, m, 20, warmup, stream, only=("five_pass_split_bf16_mfma",))
+        forms["batched_fused_fp32"] = {"ms_per_batch": ms, "evals_per_s": B / (ms * 1e-3),
+                                       "err_vs_fp64_oracle": err,
+                                       "speedup_vs_single_state":
+                                           forms["single_state_fp32_fused"]["ms_per_batch"] / ms}
+        res["forms"] = forms
     del graph
     plan.destroy()
     del m, h
