@@ -163,7 +163,8 @@ def test_stacks_share_pair_slots():
     (t_i, t_j, z_i - z_j) of all stacks is stored once (14 of the 30 pairs);
     each stack's exported tensor, gathered from the shared slots, equals the
     tensor of a plan that holds that stack alone, and each stack's field
-    matches the brute-force oracle."""
+    matches the brute-force oracle, also after re-sets to stacks with one
+    pair in common and to three equal stacks."""
     import torch
     nx, ny, dx, dy = 14, 11, 2.5, 2.0
     t1 = np.array([1.0, 0.7, 2.3, 1.5])
@@ -183,10 +184,28 @@ def test_stacks_share_pair_slots():
         assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max(), g
     m = np.random.default_rng(45).standard_normal((3, 3, 4, ny, nx))
     m /= np.linalg.norm(m, axis=1, keepdims=True)
-    h = plan.field(torch.from_numpy(m.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
-    for g in range(3):
-        ref = oracle.field(nx, ny, dx, dy, z[g], t[g], m[g])
-        assert rel_err(h[g], ref) < 1e-5, g
+    mt = torch.from_numpy(m.astype(np.float32)).cuda()
+
+    def check(t, z, slots):
+        keys = {(t[g, i], t[g, j], z[g, i] - z[g, j]) for g in range(3) for i in range(4) for j in range(i, 4)}
+        assert len(keys) == slots
+        assert plan.info().tensor_slots == slots
+        h = plan.field(mt).cpu().numpy().astype(np.float64)
+        for g in range(3):
+            ref = oracle.field(nx, ny, dx, dy, z[g], t[g], m[g])
+            assert rel_err(h[g], ref) < 1e-5, (slots, g)
+
+    check(t, z, 14)
+    # re-set: three other stacks (one pair in common: the self pair of 1.5 nm
+    # layers, 29 slots), then the same stack three times (10 slots); the table
+    # is rewritten in place
+    t3 = np.stack([t1, t2 + 0.25, t1 * 1.5])
+    z3 = np.stack([W.stack_bottoms(t3[g], gaps) for g in range(3)])
+    plan.set_thickness(t3, z3)
+    check(t3, z3, 29)
+    t4, z4 = np.stack([t2] * 3), np.stack([W.stack_bottoms(t2, gaps)] * 3)
+    plan.set_thickness(t4, z4)
+    check(t4, z4, 10)
     plan.destroy()
 
 
