@@ -1180,6 +1180,38 @@ hfd_status hfd_demag_field_noalloc(hfd_plan p, const void* m, void* h, int batch
     return run_field(p, m, h, batch, 0, (hipStream_t)stream, nullptr, nullptr, 0, -1, -1, x1);
 }
 
+// Fused path of the VJP: per run of states (as run_field chunks them) one x
+// pass of grad_h feeds both its y transform into Hh (the spectra G of the
+// thickness gradient) and the in-place fused adjoint y pass with the inverse x
+// pass (grad_m), instead of a second x pass of grad_h.
+static hfd_status adjoint_and_spectra(hfd_plan p, const void* gh, void* gm, int batch, hipStream_t s)
+{
+    const int S = 3 * p->nz, bpg = batch / p->G;
+    int chunk = chunk_for(p, batch);
+    if (!(chunk < batch && chunk_ok(p, batch, chunk))) chunk = batch;
+    const bool gen = generic_for(p, batch);
+    const int xty = xty_for(p, batch);
+    const size_t state = (size_t)S * p->ny * p->nx * p->rsz;
+    const size_t hstate = (size_t)S * p->M * p->Ly * p->csz;
+    const long long sig_stride = (long long)p->ny * p->nx;
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int g0 = b0 / bpg;
+        const int bpg_c = bpg >= chunk ? chunk : bpg;
+        const char* in_c = (const char*)gh + (size_t)b0 * state;
+        char* out_c = (char*)gm + (size_t)b0 * state;
+        const char* lp_c = (const char*)p->lp + (size_t)g0 * 2 * p->nz * p->rsz;
+        HFD_HIP(launch_xfwd(p->fp64, p->Lx, in_c, p->X1, p->nx, p->ny, sig_stride, p->nx, chunk * S,
+                            p->twx, s, xty));
+        HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, (char*)p->Hh + (size_t)b0 * hstate, p->ny,
+                            (long long)chunk * S * p->M, p->twy, s));
+        HFD_HIP(launch_fused(p->fp64, p->Ly, p->nz, p->X1, p->ny, p->M, chunk, p->Q, p->qcs,
+                             p->qslot + (size_t)g0 * p->P, p->QX, p->QY, lp_c, bpg_c, 1, p->twy, s, gen));
+        HFD_HIP(launch_xinv(p->fp64, p->Lx, p->X1, out_c, p->nx, p->ny, sig_stride, p->nx, chunk * S,
+                            p->twx, s, xty));
+    }
+    return HFD_OK;
+}
+
 hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* grad_m,
                          double* grad_thickness, int batch, void* stream)
 {
@@ -1200,15 +1232,20 @@ hfd_status hfd_demag_vjp(hfd_plan p, const void* m, const void* grad_h, void* gr
     HFD_HIP(dg.set(p->dev));
     hipStream_t s = (hipStream_t)stream;
     // (dh/dm)^T grad_h = T (dh/dm) T^-1 grad_h
-    if (grad_m) HFD_TRY(run_field(p, grad_h, grad_m, batch, 1, s));
-    if (!grad_thickness) return HFD_OK;
+    if (!grad_thickness) return run_field(p, grad_h, grad_m, batch, 1, s);
     const int nsig = batch * 3 * p->nz;
     const long long ncols = (long long)nsig * p->M;
     const long long sig_stride = (long long)p->ny * p->nx;
+    if (grad_m && path_for(p, batch) == 0) {
+        HFD_TRY(adjoint_and_spectra(p, grad_h, grad_m, batch, s));
+    } else {
+        // (the five-pass paths use Mh and Hh themselves: grad_m first)
+        if (grad_m) HFD_TRY(run_field(p, grad_h, grad_m, batch, 1, s));
+        HFD_HIP(launch_xfwd(p->fp64, p->Lx, grad_h, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
+        HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Hh, p->ny, ncols, p->twy, s));
+    }
     HFD_HIP(launch_xfwd(p->fp64, p->Lx, m, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
     HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Mh, p->ny, ncols, p->twy, s));
-    HFD_HIP(launch_xfwd(p->fp64, p->Lx, grad_h, p->X1, p->nx, p->ny, sig_stride, p->nx, nsig, p->twx, s));
-    HFD_HIP(launch_yfwd(p->fp64, p->Ly, p->X1, p->Hh, p->ny, ncols, p->twy, s));
     const int bpg = batch / p->G;
     const bool stored = (p->flags & HFD_STORE_DTENSOR) != 0;
     if (stored && !p->d_valid) {
