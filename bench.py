@@ -4,7 +4,7 @@ One step = one full field evaluation h = -N * m (x-pass R2C, y-pass with the
 explicit z-mixing, inverse x-pass) of the 256 x 256 x 8 MRAM-like stack
 (2.5 nm cells, FP32 field, tensor set up in FP64 beforehand), inputs resident
 in HBM.  Steps are replayed from a HIP graph that holds G complete evaluations
-(G: the largest divisor of K up to 10, or --graph-evals), so K steps are K / G
+(G: the largest divisor of K up to 50, or --graph-evals), so K steps are K / G
 replays.  Prints one JSON line.
 
 The line carries the roofline of the dominant kernel against the method's
@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--graph-evals", type=int, default=0,
                     help="evaluations captured per HIP graph (0: the largest divisor of --steps "
-                         "up to 10); each replay runs that many complete evaluations")
+                         "up to 50); each replay runs that many complete evaluations")
     ap.add_argument("--split", action="store_true", help="force the five-pass path")
     ap.add_argument("--compare", action="store_true",
                     help="also time every mixing path (and 64 single-state calls) on the workload, "
@@ -73,11 +73,12 @@ def parse():
 
 def graph_evals(steps: int, requested: int = 0) -> int:
     """Evaluations captured per HIP graph: `requested`, or the largest divisor
-    of `steps` up to 10, so that `steps` evaluations are a whole number of
-    replays."""
+    of `steps` up to 50, so that `steps` evaluations are a whole number of
+    replays (a time-stepping code captures its inner loop the same way; each
+    replay boundary costs about 1 us per evaluation at 10 per graph)."""
     if steps < 1:
         raise SystemExit("--steps must be >= 1")
-    G = requested or max(d for d in range(1, 11) if steps % d == 0)
+    G = requested or max(d for d in range(1, 51) if steps % d == 0)
     if G < 1 or steps % G:
         raise SystemExit(f"--steps {steps} is not a multiple of --graph-evals {G}")
     return G

@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 @pytest.mark.parametrize("steps, requested, expect", [
-    (200, 0, 10), (40, 0, 10), (12, 0, 6), (7, 0, 7), (13, 0, 1), (1, 0, 1), (400, 40, 40),
+    (200, 0, 50), (40, 0, 40), (60, 0, 30), (12, 0, 12), (53, 0, 1), (1, 0, 1), (400, 40, 40),
 ])
 def test_graph_holds_a_divisor_of_the_steps(steps, requested, expect):
     G = bench.graph_evals(steps, requested)
