@@ -69,6 +69,31 @@ def test_thickness_gradient_several_stacks_and_split_path():
     plan.destroy()
 
 
+@pytest.mark.parametrize("chunk", [0, 1, 2, 4])
+def test_both_gradients_on_the_fused_path_in_state_runs(chunk):
+    """Both gradients in one call on the fused path (one x pass of grad_h per
+    run of states feeds the gradient's spectra and the adjoint pass), with the
+    states of two stacks in one run (chunk 0: the whole batch of 4) or in
+    runs of 1, 2 or 4 states (hfd_set_fused); against the oracle per state."""
+    rng = np.random.default_rng(13)
+    nx, ny, nz, G, bpg = 12, 10, 3, 2, 2
+    t = rng.uniform(0.5, 2.5, (G, nz))
+    zb = np.stack([W.stack_bottoms(t[g], [0.3, 0.0]) for g in range(G)])
+    m = np.stack([W.random_unit(rng, (nz, ny, nx)) for _ in range(G * bpg)])
+    g = rng.standard_normal(m.shape)
+    plan = hfd.Plan(nx, ny, 2.0, 1.5, t, zb, batch_max=G * bpg)
+    assert plan.info().fused
+    plan.set_fused(G * bpg, chunk)
+    gm, gt = _vjp(plan, m, g)
+    for b in range(G * bpg):
+        k = b // bpg
+        ref_t = oracle.thickness_grad(nx, ny, 2.0, 1.5, zb[k], t[k], m[b], g[b])
+        assert np.abs(gt[b] - ref_t).max() < 2e-5 * np.abs(ref_t).max(), (chunk, b)
+        ref_m = oracle.field(nx, ny, 2.0, 1.5, zb[k], t[k], g[b], transpose=True)
+        assert np.abs(gm[b] - ref_m).max() < 1e-5 * np.abs(ref_m).max(), (chunk, b)
+    plan.destroy()
+
+
 def test_dot_product_identity_on_gpu():
     """<g, A m> = <A^T g, m> with both operators from the GPU (FP64)."""
     import torch
