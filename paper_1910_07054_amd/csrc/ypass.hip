@@ -67,13 +67,11 @@ hipError_t launch_yinv(bool fp64, int LY, const void* in, void* out, int n_out, 
     HFD_Y_CASES(yinv_t, float, in, out, n_out, ncols, twy, s)
 }
 
-hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
-                              const void* Q, long long qcs, const int* qslot, int QX, int QY,
-                              const void* lp, int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
+template <int IB>
+static hipError_t mix_pairs_t(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
+                              const void* Q, long long qcs, const int* qslot, int QY, const void* lp,
+                              int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
 {
-    (void)QX;
-    if (nkx <= 0) return hipSuccess;
-    constexpr int IB = 4;
     const int ngrp = (nz + IB - 1) / IB;
     const long long tiles = (long long)((LY / 2 + 31) / 32) * nkx * B;
     const long long nblk = (tiles + 7) / 8 * 8 * ngrp;
@@ -88,6 +86,20 @@ hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M
                            (const cpx<float>*)Mh, (cpx<float>*)Hh, nz, M, LY, (const float*)Q, qcs,
                            qslot, QY, (const float*)lp, bpg, adjoint, kx0, nkx, B);
     return hipGetLastError();
+}
+
+// 4 target layers per lane up to 15 layers, 2 from 16 on (measured at 32 layers:
+// 0.396 ms against 0.421 ms for 4 and 0.541 ms for 8; at 4 layers 4 is
+// slightly ahead)
+hipError_t launch_mix_generic(bool fp64, const void* Mh, void* Hh, int nz, int M, int LY, int B,
+                              const void* Q, long long qcs, const int* qslot, int QX, int QY,
+                              const void* lp, int bpg, int adjoint, int kx0, int nkx, hipStream_t s)
+{
+    (void)QX;
+    if (nkx <= 0) return hipSuccess;
+    if (nz >= 16)
+        return mix_pairs_t<2>(fp64, Mh, Hh, nz, M, LY, B, Q, qcs, qslot, QY, lp, bpg, adjoint, kx0, nkx, s);
+    return mix_pairs_t<4>(fp64, Mh, Hh, nz, M, LY, B, Q, qcs, qslot, QY, lp, bpg, adjoint, kx0, nkx, s);
 }
 
 }  // namespace hfd
