@@ -47,6 +47,18 @@ def test_algorithmic_bytes_and_flops_per_launch():
     assert 0.7e9 < f8 < 0.76e9 and f0 > 0
 
 
+def test_distinct_tensor_bytes():
+    """The C5 line beside the per-stack formula: 16 states of 256^2 x 10 and
+    the 205 distinct pair tensors of the 16 candidates, 0.577 GB; with one
+    stack and all pairs distinct the two counts agree."""
+    r = bench.with_distinct_tensor({"kernel_ms": 1.0}, 256, 256, 10, 16, 205)
+    assert r["alg_bytes_distinct"] == 16 * 24 * 256 * 256 * 10 + 24 * 257 * 257 * 205
+    assert abs(r["alg_bytes_distinct"] / 1e9 - 0.577) < 0.001
+    assert abs(r["frac_distinct"] - r["alg_bytes_distinct"] / 1e-3 / 8e12) < 1e-12
+    r1 = bench.with_distinct_tensor({"kernel_ms": 1.0}, 256, 256, 8, 1, 36)
+    assert r1["alg_bytes_distinct"] == bench.algorithmic_bytes(256, 256, 8, 1)
+
+
 def test_percentiles():
     p = bench.percentiles(np.arange(1, 101, dtype=float))
     assert p["median"] == 50.5 and p["n"] == 100 and p["p10"] < p["median"] < p["p90"]
