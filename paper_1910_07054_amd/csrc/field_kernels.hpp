@@ -518,7 +518,9 @@ struct MirrorPoints {
 
 template <int LY>
 struct FusedShape {
-    static constexpr int NT = LY < 64 ? 64 : LY;
+    // one thread per frequency from 512-point columns on; shorter columns
+    // get 512 threads too, so that more of their transforms run at once
+    static constexpr int NT = LY < 512 ? 512 : LY;
 };
 
 // ---------------------------------------------------------------------------
