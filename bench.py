@@ -124,7 +124,8 @@ def fused_kernel_bytes(nx, ny, nz, B, Lx, Ly):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "M0_fused_traffic.txt")
 FUSED_SOURCES = ["hfd_device.hpp", "field_kernels.hpp", "fused.hip", "fused_exact.hpp",
-                 "fused_exact_1.hip", "fused_exact_2.hip", "fused_exact_3.hip", "fused_exact_4.hip"]
+                 "fused_exact_1.hip", "fused_exact_2.hip", "fused_exact_3.hip", "fused_exact_4.hip",
+                 "fused_exact_5.hip"]
 
 
 def measured_traffic(workload):

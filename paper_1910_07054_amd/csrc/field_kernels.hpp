@@ -702,8 +702,8 @@ __global__ __launch_bounds__(FusedShape<LY>::NT) void k_ymix_fused(
 }
 
 // ---------------------------------------------------------------------------
-// Fused y pass for a stack of exactly NZ layers (single precision, 512- or
-// 1024-point columns, 512 threads): the same three phases as ymix_column, with every loop over
+// Fused y pass for a stack of exactly NZ layers (single precision, 256-, 512-
+// or 1024-point columns, 512 threads): the same three phases as ymix_column, with every loop over
 // layers and layer pairs unrolled.  A lane's 3 NZ input values sit in
 // registers for the whole mixing, which walks the NZ (NZ + 1) / 2 stored pairs
 // in order (i, j >= i) and applies each block both ways; the tensor entries
@@ -731,7 +731,11 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
     constexpr int TPL = LY / NT;           // frequency pairs per lane pair
     constexpr int LYP = fft_region(LY);    // LDS slots per signal
     constexpr int NR = (S + NG - 1) / NG;  // signals per wave, at most
-    static_assert(sizeof(R) == 4 && GT == 64, "single precision, one transform per wavefront");
+    // one transform per wavefront (512- and 1024-point columns), or two
+    // (256-point columns: each half-wave transforms its own signal, so the
+    // column reads and writes use per-lane addresses instead of descriptors)
+    static_assert(sizeof(R) == 4 && (GT == 64 || GT == 32), "single precision, 256 to 1024 points");
+    constexpr bool WHOLE_WAVE = GT == 64;
     // 512-point columns: block 0 runs the packed column 0 with the generic
     // body (one thread per frequency, as here); longer columns leave column 0
     // to a separate launch of k_ymix_fused and start at kx = 1
@@ -763,14 +767,24 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
         cpx<R> xin[NR][V];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
-            if (s < S) {
-                const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
-                fft_first_loads<R, LY, true>(xin[r], g, [&](int pos) -> cpx<R> {
-                    return __builtin_bit_cast(cpx<R>, __builtin_amdgcn_raw_buffer_load_b64(
-                                                          src, pos * (int)sizeof(cpx<R>), 0, 0));
-                });
+            if constexpr (WHOLE_WAVE) {
+                const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
+                if (s < S) {
+                    const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
+                    fft_first_loads<R, LY, true>(xin[r], g, [&](int pos) -> cpx<R> {
+                        return __builtin_bit_cast(cpx<R>, __builtin_amdgcn_raw_buffer_load_b64(
+                                                              src, pos * (int)sizeof(cpx<R>), 0, 0));
+                    });
+                }
+            } else {
+                const int s = grp + r * NG;
+                if (s < S) {
+                    const cpx<R>* src = col + s * sstride;
+                    fft_first_loads<R, LY, true>(xin[r], g, [&](int pos) -> cpx<R> {
+                        return pos < ny ? src[pos] : cpx<R>{R(0), R(0)};
+                    });
+                }
             }
         }
         // the first PRE tensor pairs are requested behind the column values
@@ -854,18 +868,31 @@ __global__ __launch_bounds__(ExactShape<LY>::NT) void k_ymix_fused_nz(
         tw.load(g, twy, 1);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
-            if (s < S) {
-                const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
-                cpx<R>* reg = sh + s * LYP;
-                wave_fft<R, LY, true, false, true>(
-                    reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
-                    [&](int pos, cpx<R> v) {
-                        __builtin_amdgcn_raw_buffer_store_b64(
-                            __builtin_bit_cast(__attribute__((__vector_size__(8))) unsigned, v), dst,
-                            pos * (int)sizeof(cpx<R>), 0, 0);
-                    });
+            if constexpr (WHOLE_WAVE) {
+                const int s = __builtin_amdgcn_readfirstlane(grp + r * NG);
+                if (s < S) {
+                    const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(col + s * sstride), (short)0, cbytes, 0x00020000);
+                    cpx<R>* reg = sh + s * LYP;
+                    wave_fft<R, LY, true, false, true>(
+                        reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
+                        [&](int pos, cpx<R> v) {
+                            __builtin_amdgcn_raw_buffer_store_b64(
+                                __builtin_bit_cast(__attribute__((__vector_size__(8))) unsigned, v),
+                                dst, pos * (int)sizeof(cpx<R>), 0, 0);
+                        });
+                }
+            } else {
+                const int s = grp + r * NG;
+                if (s < S) {
+                    cpx<R>* dst = col + s * sstride;
+                    cpx<R>* reg = sh + s * LYP;
+                    wave_fft<R, LY, true, false, true>(
+                        reg, g, tw, [&](int pos) -> cpx<R> { return reg[pos]; },
+                        [&](int pos, cpx<R> v) {
+                            if (pos < ny) dst[pos] = v;
+                        });
+                }
             }
         }
     }

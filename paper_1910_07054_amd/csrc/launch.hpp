@@ -59,9 +59,10 @@ hipError_t launch_fused(bool fp64, int LY, int nz, void* X, int ny, int M, int B
                         long long qcs, const int* qslot, int QX, int QY, const void* lp, int bpg,
                         int adjoint, const void* twy, hipStream_t s, bool generic = false);
 
-// exact-layer-count fused y pass (single precision; LY = 512 with 1 <= nz <=
-// 10, LY = 1024 with 1 <= nz <= 4): grid (M, bpg, G); units 1-3 cover 1-4, 5-7
-// and 8-10 layers of 512-point columns, unit 4 the 1024-point columns
+// exact-layer-count fused y pass (single precision; LY = 256 or 512 with
+// 1 <= nz <= 10, LY = 1024 with 1 <= nz <= 4): grid (M, bpg, G); units 1-3
+// cover 1-4, 5-7 and 8-10 layers of 512-point columns, unit 4 the 1024-point
+// columns, unit 5 the 256-point columns
 hipError_t launch_fused_exact_1(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
                                 const void* Q, long long qcs, const int* qslot, int QY,
                                 const void* lp, const void* tw, hipStream_t s);
@@ -74,15 +75,19 @@ hipError_t launch_fused_exact_3(int nz, int adjoint, void* X, int ny, int M, int
 hipError_t launch_fused_exact_4(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
                                 const void* Q, long long qcs, const int* qslot, int QY,
                                 const void* lp, const void* tw, hipStream_t s);
+hipError_t launch_fused_exact_5(int nz, int adjoint, void* X, int ny, int M, int bpg, int G,
+                                const void* Q, long long qcs, const int* qslot, int QY,
+                                const void* lp, const void* tw, hipStream_t s);
 inline bool fused_exact_supported(bool fp64, int LY, int nz)
 {
-    return !fp64 && nz >= 1 && ((LY == 512 && nz <= 10) || (LY == 1024 && nz <= 4));
+    return !fp64 && nz >= 1 && ((LY == 256 && nz <= 10) || (LY == 512 && nz <= 10) || (LY == 1024 && nz <= 4));
 }
 inline hipError_t launch_fused_exact(int LY, int nz, int adjoint, void* X, int ny, int M, int bpg,
                                      int G, const void* Q, long long qcs, const int* qslot, int QY,
                                      const void* lp, const void* tw, hipStream_t s)
 {
     if (LY == 1024) return launch_fused_exact_4(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
+    if (LY == 256) return launch_fused_exact_5(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
     if (nz <= 4) return launch_fused_exact_1(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
     if (nz <= 7) return launch_fused_exact_2(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);
     return launch_fused_exact_3(nz, adjoint, X, ny, M, bpg, G, Q, qcs, qslot, QY, lp, tw, s);

@@ -397,6 +397,34 @@ def test_exact_kernel_1024_point_columns_field_and_adjoint():
     plan.destroy()
 
 
+@pytest.mark.parametrize("nz", [1, 3, 7, 10])
+def test_exact_kernel_256_point_columns_every_layer_count(nz):
+    """ny in (64, 128] pads to Ly = 256: the exact-layer kernel with two
+    transforms per wavefront (each half-wave its own signal) against the
+    run-time layer-count kernel on the same plan (FP32 both, element by
+    element), and the field and its transpose against the oracle."""
+    import torch
+    wl = W.small_case(9, 100, nz, seed=660 + nz, batch=2)
+    plan = plan_for(wl)
+    assert plan.info().Ly == 256 and plan.info().fused
+    plan.set_fused(2, 0, generic=False)
+    h, mused = run_field(plan, wl.m)
+    plan.set_fused(2, 0, generic=True)
+    hg, _ = run_field(plan, wl.m)
+    assert np.abs(h - hg).max() <= 1e-6 * np.abs(hg).max()
+    plan.set_fused(2, 0, generic=False)
+    g = np.random.default_rng(670 + nz).standard_normal(wl.m.shape).astype(np.float32)
+    gm, _ = plan.vjp(None, torch.from_numpy(g).cuda(), want_m=True, want_t=False)
+    gm = gm.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        ref = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0], mused[b])
+        assert rel_err(h[b], ref) < 1e-5, b
+        reft = oracle.field(wl.nx, wl.ny, wl.dx, wl.dy, wl.z_bottom[0], wl.thickness[0],
+                            g[b].astype(np.float64), transpose=True)
+        assert rel_err(gm[b], reft) < 1e-5, b
+    plan.destroy()
+
+
 @pytest.mark.parametrize("ny", [140, 300])
 def test_chunked_runs_match_oracle_with_two_stacks(ny):
     """Batch of 6 states over 2 stacks (3 states each) evaluated in runs of 1,
