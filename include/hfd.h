@@ -230,8 +230,9 @@ hfd_status hfd_set_path(hfd_plan plan, int batch, int path, int x_tile);
  *            divide batch, and a run must lie inside one stack or cover whole
  *            stacks (chunk divides batch / n_geom, or is a multiple of it).
  *   generic  1: the y pass with the layer count read at run time even where a
- *            kernel compiled for the exact layer count exists (FP32, 512- and
- *            1024-point columns); 0: the exact kernel where it exists.
+ *            kernel compiled for the exact layer count exists (FP32; 256- and
+ *            512-point columns up to 10 layers, 1024-point columns up to 4);
+ *            0: the exact kernel where it exists.
  * HFD_EINVAL for other values. */
 hfd_status hfd_set_fused(hfd_plan plan, int batch, int chunk, int generic);
 

@@ -1,7 +1,7 @@
 // Instances of the fused y-pass (y-DFT, z-mixing, inverse y-DFT in LDS):
 // the generic kernel (layer count up to NZMAX at run time); single-precision
-// 512-point columns of up to 10 layers and 1024-point columns of up to 4 go
-// to the exact-layer-count kernels (fused_exact_*.hip).
+// 256- and 512-point columns of up to 10 layers and 1024-point columns of up
+// to 4 go to the exact-layer-count kernels (fused_exact_*.hip).
 #include "field_kernels.hpp"
 #include "launch.hpp"
 
