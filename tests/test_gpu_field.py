@@ -397,14 +397,15 @@ def test_exact_kernel_1024_point_columns_field_and_adjoint():
     plan.destroy()
 
 
-@pytest.mark.parametrize("nz", [1, 3, 7, 10])
-def test_exact_kernel_256_point_columns_every_layer_count(nz):
+@pytest.mark.parametrize("nz,ny", [(1, 100), (3, 100), (7, 100), (10, 100), (4, 65), (4, 128)])
+def test_exact_kernel_256_point_columns_every_layer_count(nz, ny):
     """ny in (64, 128] pads to Ly = 256: the exact-layer kernel with two
     transforms per wavefront (each half-wave its own signal) against the
     run-time layer-count kernel on the same plan (FP32 both, element by
-    element), and the field and its transpose against the oracle."""
+    element), and the field and its transpose against the oracle; the
+    shortest and the longest columns of that length included."""
     import torch
-    wl = W.small_case(9, 100, nz, seed=660 + nz, batch=2)
+    wl = W.small_case(9, ny, nz, seed=660 + nz + ny, batch=2)
     plan = plan_for(wl)
     assert plan.info().Ly == 256 and plan.info().fused
     plan.set_fused(2, 0, generic=False)
